@@ -1,0 +1,177 @@
+"""Benchmark of the characteristic (spatial-advection) step on one MI355X.
+
+Workload: 32^3 x-nodes on [-12,12)^3 times 16^3 k-nodes on [-4,4)^3 (134,217,728
+phase-space points), patches of 8 cells, ghost width 6, dt = 0.02, seeded 4-packet
+Gaussian mixture, FP32 storage and arithmetic.  A step is one pass of the whole hot
+path: the x1, x2 and x3 sweeps of every point.
+
+The field is resident in HBM before timing starts.  Each step is replayed as a HIP
+graph on the library's stream; a HIP event is recorded on that stream between steps,
+which gives the per-step latency distribution (p50/p99) and the mean duration of the
+dominant kernel (one kernel per step under the cube schedule).  Beside it: the plain
+FP64 form (three launches per step, eager) and the FP64 CPU oracle timed on a bounded
+sample of k-points (cpu_baseline), whose result at those k-points also gives the
+error of the timed GPU run.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = ["chasm_line.hpp", "chasm_kernels.hpp", "chasm_launch.hpp"]
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2205_02380_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload, {}).get(kernel)
+    if not e or e.get("kernel_digest") != kernel_digest():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def time_steps(adv, torch, steps, stream):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        adv.step(1)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])     # ms
+    return ev[0].elapsed_time(ev[steps]) / 1e3, per
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--fp64-steps", type=int, default=20)
+    ap.add_argument("--cpu-kpoints", type=int, default=24)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: --gpus {args.gpus} is not supported "
+              "(the advection is independent per k-point; see the sharding notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2205_02380_amd import chasm, inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    w = inputs.workload("C2")
+    g = w.grid
+    points = g.points
+
+    # ---- FP32, cube schedule, graph replay ------------------------------------------
+    f = torch.empty(g.shape(), dtype=torch.float32, device=dev)
+    coef, gx, gk = inputs.packet_factors(g, w.packets)
+    inputs.fill_separable(f, coef, gx, gk)
+    kidx = inputs.k_sample(g, args.cpu_kpoints / g.nkpts, 40)
+    start_cubes = np.stack([f[i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in kidx])
+    torch.cuda.synchronize()
+    adv = chasm.Advect(f, g, w.patch, w.ghost, w.dt, graph=True, stream=stream)
+    sched = adv.schedule
+    adv.step(args.warmup)
+    torch.cuda.synchronize()
+    total_s, per = time_steps(adv, torch, args.steps, stream)
+    adv.close()
+    value = points * args.steps / total_s
+    ms_per_step = total_s * 1e3 / args.steps
+    kernel = "k_cube" if sched == "cube" else "k_slab+k_pencil"
+    bytes_alg = 8.0 * points                       # read + write of every FP32 value, once per launch
+    mean_kernel_s = float(per.mean()) / 1e3
+    achieved = bytes_alg / mean_kernel_s / 1e9
+    gpu_cubes = np.stack([f[i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in kidx])
+    del f
+    torch.cuda.empty_cache()
+
+    # ---- plain FP64 one-job form ---------------------------------------------------------
+    f64 = torch.empty(g.shape(), dtype=torch.float64, device=dev)
+    inputs.fill_separable(f64, coef, gx, gk)
+    adv64 = chasm.Advect(f64, g, w.patch, w.ghost, w.dt, schedule="plain", stream=stream)
+    adv64.step(2)
+    torch.cuda.synchronize()
+    t64, per64 = time_steps(adv64, torch, args.fp64_steps, stream)
+    adv64.close()
+    value64 = points * args.fp64_steps / t64
+    del f64
+    torch.cuda.empty_cache()
+
+    # ---- CPU baseline: the FP64 oracle on a bounded k-sample ---------------------------
+    cpu = None
+    err = None
+    if not args.no_cpu:
+        import oracle
+        nthreads = len(os.sched_getaffinity(0))
+        nst = args.warmup + args.steps
+        t0 = time.perf_counter()
+        ref = oracle.advect6d(start_cubes, g.nx, g.hx, g.nk, g.k_lo, g.hk, w.patch, w.ghost, w.dt, nst,
+                              kidx=kidx, nthreads=nthreads)
+        tc = time.perf_counter() - t0
+        cpu = {"value": len(kidx) * g.cube * nst / tc, "unit": "point-updates/s", "cores": nthreads,
+               "kind": "oracle",
+               "sample": f"{len(kidx)} seeded k-points x {g.cube} x-points x {nst} steps "
+                         f"({tc:.1f} s wall, FP64, OpenMP over k-points)"}
+        err = float(np.max(np.abs(gpu_cubes - ref)) / np.max(np.abs(ref)))
+
+    traffic = measured_traffic(kernel, "C2")
+    line = {
+        "metric": "6-D point-updates/s FP32 vs FP64 plain at <=1e-5 rel err; p50/p99 step latency",
+        "value": value,
+        "unit": "point-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded 4-packet Gaussian mixture, generated on the GPU)",
+        "config": {"workload": "32^3 x [-12,12)^3 by 16^3 k [-4,4)^3, 134217728 points, patch 8, ghost 6, "
+                               "dt 0.02, FP32, one job", "schedule": sched, "graph": True},
+        "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
+                            "mean": float(per.mean())},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+                     "alg_bytes_per_launch": bytes_alg},
+        "fp64_plain": {"value": value64, "unit": "point-updates/s", "ms_per_step": t64 * 1e3 / args.fp64_steps,
+                       "schedule": "plain (3 launches/step, eager)", "alg_bytes_per_point_update": 48},
+        "fp32_vs_fp64_plain": value / value64,
+        "err_vs_oracle": err,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * chasm_advect.h -- C ABI of the MI355X (gfx950) characteristic step of the CHASM
+ * scheme for the 6-D Wigner equation.
+ *
+ * Paper: Y. Xiong, Y. Zhang, S. Shao, "A characteristic-spectral-mixed scheme for
+ * six-dimensional Wigner-Coulomb dynamics", arXiv:2205.02380.
+ *
+ * The library advances a phase-space function f(x, k) along the characteristic flow
+ * A_tau(x, k) = (x - k dt, k) of the free-streaming Wigner equation (Sec. 2.2,
+ * eq. 2.6, hbar = m = 1):  f_new(x, k) = f(x - k dt, k).  The shift is interpolated
+ * with patch-local cubic B-splines (Sec. 3.1): every patch of M cells solves its own
+ * spline coefficients, closed by the perfectly matched boundary condition (PMBC,
+ * eqs. 3.4-3.5) whose stencils reach g nodes into the neighbouring patches, and
+ * the patch whose cells contain a departure point evaluates it (Sec. 3.1.3).  The
+ * 3-D shift is applied as three successive axis sweeps x1, x2, x3 (the tensor-product
+ * spline of Sec. 3.2, eqs. 3.11-3.12).
+ *
+ * No C++ types and no exceptions cross this boundary.  All device pointers are plain
+ * HIP device addresses; hip_stream is a hipStream_t passed as void* (NULL = the
+ * default stream).
+ *
+ * Field layout (caller-owned device memory, contiguous):
+ *   f[b][k3][k2][k1][x3][x2][x1], x1 fastest, b < nbatch independent fields of the
+ *   same grid.  Element type float (CHASM_F32) or double (CHASM_F64).
+ * Grids are half-open: x_{d,i} = x_lo[d] + i*h_d, h_d = (x_hi[d]-x_lo[d])/nx[d],
+ *   k_{d,i} = k_lo[d] + i*hk_d, hk_d = (k_hi[d]-k_lo[d])/nk[d].
+ * Patches along an axis of N nodes: p = ceil((N-1)/M) patches of M cells sharing end
+ *   nodes (eq. 3.1), the last one possibly shorter.
+ *
+ * Errors: every call returns a chasm_status; on failure chasm_advect_last_error()
+ * returns a message for the calling thread.  A handle whose device work failed is
+ * poisoned and returns CHASM_ESTATE until destroyed.  Handles are not thread-safe:
+ * one owning thread per handle.
+ */
+#ifndef CHASM_ADVECT_H
+#define CHASM_ADVECT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chasm_advect_s* chasm_advect_t;   /* opaque handle */
+
+typedef enum {
+    CHASM_OK = 0,
+    CHASM_EINVAL = -1,        /* invalid argument or descriptor */
+    CHASM_ENOMEM = -2,        /* device or host allocation failed */
+    CHASM_EDEVICE = -3,       /* a HIP call or kernel launch failed */
+    CHASM_ESTATE = -4,        /* handle poisoned by an earlier device failure */
+    CHASM_EUNSUPPORTED = -5   /* valid, but no kernel is built for this shape */
+} chasm_status;
+
+typedef enum { CHASM_F32 = 0, CHASM_F64 = 1 } chasm_dtype;
+
+typedef enum {
+    /* The paper's closure: interface slopes from rows of the inverse of the
+     * natural-BC global spline matrix, truncated to |j - I| <= ghost (eqs. 3.3-3.5);
+     * ghost splines beyond the outer line ends carry coefficient 0 (Sec. 3.1.3). */
+    CHASM_CLOSURE_PMBC = 0,
+    /* Variant not in the paper: the same rows plus the minimum-norm correction that
+     * makes them exact for cubic data, and outer ghost coefficients extrapolated by a
+     * zero fourth difference, so cubic polynomials in x are advected exactly.
+     * Needs ghost >= 3. */
+    CHASM_CLOSURE_POLY3 = 1
+} chasm_closure;
+
+typedef enum {
+    CHASM_SCHED_AUTO = 0,     /* CUBE when the x-cube fits in LDS, else SLAB */
+    CHASM_SCHED_CUBE = 1,     /* one launch per step, all three sweeps in LDS */
+    CHASM_SCHED_SLAB = 2,     /* two launches per step: x1+x2 on x3-slabs, then x3 */
+    CHASM_SCHED_PLAIN = 3     /* three launches per step, one per axis */
+} chasm_schedule;
+
+enum {
+    CHASM_FLAG_REDUCE_EACH_STEP = 1u << 0,   /* record FP64 diagnostics after every step */
+    CHASM_FLAG_GRAPH = 1u << 1               /* replay each step as a captured HIP graph */
+};
+
+typedef struct {
+    int32_t nx[3];            /* x nodes per axis; the kernels need nx[0]==nx[1]==nx[2] */
+    int32_t nk[3];            /* k nodes per axis (>= 1) */
+    double x_lo[3], x_hi[3];  /* half-open x extents */
+    double k_lo[3], k_hi[3];  /* half-open k extents */
+    int32_t patch[3];         /* cells per patch M_d (>= 1); the kernels need equal M_d */
+    int32_t ghost;            /* PMBC stencil half-width g = n_nb (>= 1; >= 3 for POLY3) */
+    double dt;                /* time step (hbar = m = 1) */
+    int32_t dtype;            /* chasm_dtype */
+    int32_t closure;          /* chasm_closure */
+    int32_t nbatch;           /* independent fields of this grid, leading dimension b (>= 1) */
+    uint32_t flags;           /* CHASM_FLAG_* */
+    int32_t schedule;         /* chasm_schedule */
+    int32_t history_cap;      /* steps of diagnostics kept with REDUCE_EACH_STEP (0: 1024) */
+} chasm_advect_desc;
+
+/* Create a handle that advances the caller's field f_dev in place.
+ * Builds the per-axis FP64 tables on the host (interface stencils, patch factors,
+ * per-k shift weights; eqs. 3.4-3.8), copies them to the device, and picks kernels.
+ * f_dev: device pointer, 16-byte aligned, nbatch*prod(nk)*prod(nx) elements of the
+ *   dtype; owned by the caller, never freed by the library, must outlive the handle.
+ * hip_stream: stream all work of this handle is issued on.
+ * Errors: EINVAL (bad descriptor or pointer), EUNSUPPORTED (no kernel for this
+ *   shape), ENOMEM, EDEVICE. */
+chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, void* hip_stream,
+                                 chasm_advect_t* out);
+
+/* Advance the field by nsteps steps of dt (each step: x1, x2, x3 sweeps, Sec. 3.2).
+ * Asynchronous on the handle's stream.  nsteps == 0 is a no-op; nsteps < 0 -> EINVAL. */
+chasm_status chasm_advect_step(chasm_advect_t h, int32_t nsteps);
+
+/* FP64 diagnostics of the current field (Sec. 5: grid sums times the cell volume
+ * V = prod h_d * prod hk_d, summed over the batch): mass = V sum f; l2 = V sum f^2
+ * (nullable); moments6 = V sum x_d f (d = 1..3) then V sum k_d f (nullable).
+ * Synchronises the handle's stream. */
+chasm_status chasm_advect_mass(chasm_advect_t h, double* mass, double* l2, double* moments6);
+
+/* Per-batch-member diagnostics of the current field: out[b*8 + i], i = mass, l2,
+ * sum x1 f, x2, x3, k1, k2, k3 (all times V).  out holds nbatch*8 doubles (host).
+ * Synchronises the handle's stream. */
+chasm_status chasm_advect_diagnostics(chasm_advect_t h, double* out);
+
+/* Diagnostics recorded by CHASM_FLAG_REDUCE_EACH_STEP, oldest first:
+ * out[s*nbatch*8 + b*8 + i] for s < *n_out (at most max_steps, host memory).
+ * Synchronises the handle's stream. */
+chasm_status chasm_advect_history(chasm_advect_t h, double* out, int32_t max_steps, int32_t* n_out);
+
+/* Advance several handles by nsteps[i] steps each.  Handles with the same dtype,
+ * grid shape, patch and ghost width share one launch per sweep (their items are
+ * concatenated in a device work list); all handles must use the same stream.
+ * Asynchronous. */
+chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const int32_t* nsteps);
+
+/* Device bytes the library allocates for a handle with this descriptor (tables,
+ * partials, history), not counting the caller's field. */
+chasm_status chasm_advect_workspace_bytes(const chasm_advect_desc* desc, size_t* bytes);
+
+/* Schedule actually used by a handle (after AUTO resolution). */
+chasm_status chasm_advect_schedule(chasm_advect_t h, int32_t* schedule);
+
+/* Release everything the library allocated for h.  Synchronises its stream.
+ * NULL is a no-op. */
+chasm_status chasm_advect_destroy(chasm_advect_t h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* chasm_advect_last_error(void);
+
+/* Library version string. */
+const char* chasm_advect_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHASM_ADVECT_H */

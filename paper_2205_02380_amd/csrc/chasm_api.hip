@@ -1,0 +1,497 @@
+// chasm_api.hip -- C ABI of the characteristic (spatial-advection) step:
+// descriptor validation, FP64 table upload, kernel selection, step scheduling
+// (eager or HIP-graph replay), FP64 diagnostics.  See include/chasm_advect.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/chasm_advect.h"
+#include "chasm_kernels.hpp"
+#include "chasm_registry.hpp"
+#include "chasm_tables.hpp"
+
+namespace chasm {
+
+// ---------------------------------------------------------------------------
+// Kernel registry: every compiled (dtype, N, M, G).
+#define CHASM_DECL(T, N, M, G) extern template const KernelSet* kernel_set<T, N, M, G>();
+CHASM_SHAPES(CHASM_DECL)
+#undef CHASM_DECL
+
+static const std::vector<const KernelSet*>& registry()
+{
+    static const std::vector<const KernelSet*> all = [] {
+        std::vector<const KernelSet*> v;
+#define CHASM_REG(T, N, M, G) v.push_back(kernel_set<T, N, M, G>());
+        CHASM_SHAPES(CHASM_REG)
+#undef CHASM_REG
+        return v;
+    }();
+    return all;
+}
+
+// Smallest compiled window G >= g for (dtype, N, M).
+static const KernelSet* find_kernels(int dtype, int N, int M, int g)
+{
+    const KernelSet* best = nullptr;
+    for (const KernelSet* k : registry()) {
+        if (k->dtype != dtype || k->N != N || k->M != M || k->G < g) continue;
+        if (!best || k->G < best->G) best = k;
+    }
+    return best;
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, long long rows_per_batch,
+                                                  FinalizeArgs a, double* __restrict__ out,
+                                                  double* __restrict__ hist, int* __restrict__ counter,
+                                                  int hist_cap, int nbatch)
+{
+    __shared__ double red[256][NRED];
+    __shared__ int slot;
+    if (threadIdx.x == 0) slot = hist ? (*counter % hist_cap) : 0;
+    __syncthreads();
+    for (int b = 0; b < nbatch; ++b) {
+        double acc[NRED];
+        for (int v = 0; v < NRED; ++v) acc[v] = 0.0;
+        const double* p = partials + (long long)b * rows_per_batch * NRED;
+        for (long long r = threadIdx.x; r < rows_per_batch; r += 256)
+            for (int v = 0; v < NRED; ++v) acc[v] += p[r * NRED + v];
+        for (int v = 0; v < NRED; ++v) red[threadIdx.x][v] = acc[v];
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                for (int v = 0; v < NRED; ++v) red[threadIdx.x][v] += red[threadIdx.x + w][v];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double* S = red[0];
+            double r[NRED];
+            r[0] = a.vol * S[0];
+            r[1] = a.vol * S[1];
+            for (int d = 0; d < 3; ++d) {
+                r[2 + d] = a.vol * (a.xlo[d] * S[0] + a.hx[d] * S[2 + d]);
+                r[5 + d] = a.vol * (a.klo[d] * S[0] + a.hk[d] * S[5 + d]);
+            }
+            for (int v = 0; v < NRED; ++v) out[b * NRED + v] = r[v];
+            if (hist)
+                for (int v = 0; v < NRED; ++v) hist[((long long)slot * nbatch + b) * NRED + v] = r[v];
+        }
+        __syncthreads();
+    }
+    if (hist && threadIdx.x == 0) *counter = *counter + 1;
+}
+
+}  // namespace chasm
+
+using namespace chasm;
+
+// ---------------------------------------------------------------------------
+// Handle.
+struct chasm_advect_s {
+    chasm_advect_desc desc;
+    void* f = nullptr;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    const KernelSet* ks = nullptr;
+    int schedule = CHASM_SCHED_AUTO;
+    JobDev job{};
+    FinalizeArgs fin{};
+    void* tables = nullptr;          // device block: FP64 tables then FP32 mirror, int shifts
+    double* partials = nullptr;      // [rows][NRED]
+    long long partial_rows = 0;      // rows per batch member when reducing each step
+    double* last = nullptr;          // [nbatch][NRED]
+    double* hist = nullptr;          // [cap][nbatch][NRED]
+    int* counter = nullptr;
+    int hist_cap = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    bool poisoned = false;
+};
+
+static thread_local std::string g_err;
+
+static chasm_status fail(chasm_status st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+
+static chasm_status hip_fail(chasm_advect_t h, hipError_t e, const char* what)
+{
+    if (h) h->poisoned = true;
+    return fail(CHASM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static chasm_status validate(const chasm_advect_desc* d, const KernelSet** ks_out)
+{
+    if (!d) return fail(CHASM_EINVAL, "desc is NULL");
+    for (int i = 0; i < 3; ++i) {
+        if (d->nx[i] < 2) return fail(CHASM_EINVAL, "nx must be >= 2 on every axis");
+        if (d->nk[i] < 1) return fail(CHASM_EINVAL, "nk must be >= 1 on every axis");
+        if (!(d->x_hi[i] > d->x_lo[i]) || !std::isfinite(d->x_lo[i]) || !std::isfinite(d->x_hi[i]))
+            return fail(CHASM_EINVAL, "x extents must be finite with x_hi > x_lo");
+        if (!(d->k_hi[i] > d->k_lo[i]) || !std::isfinite(d->k_lo[i]) || !std::isfinite(d->k_hi[i]))
+            return fail(CHASM_EINVAL, "k extents must be finite with k_hi > k_lo");
+        if (d->patch[i] < 1) return fail(CHASM_EINVAL, "patch must be >= 1");
+    }
+    if (d->ghost < 1) return fail(CHASM_EINVAL, "ghost must be >= 1");
+    if (!std::isfinite(d->dt)) return fail(CHASM_EINVAL, "dt must be finite");
+    if (d->dtype != CHASM_F32 && d->dtype != CHASM_F64) return fail(CHASM_EINVAL, "unknown dtype");
+    if (d->closure != CHASM_CLOSURE_PMBC && d->closure != CHASM_CLOSURE_POLY3)
+        return fail(CHASM_EINVAL, "unknown closure");
+    if (d->closure == CHASM_CLOSURE_POLY3 && d->ghost < 3) return fail(CHASM_EINVAL, "POLY3 closure needs ghost >= 3");
+    if (d->nbatch < 1) return fail(CHASM_EINVAL, "nbatch must be >= 1");
+    if (d->schedule < CHASM_SCHED_AUTO || d->schedule > CHASM_SCHED_PLAIN) return fail(CHASM_EINVAL, "unknown schedule");
+    if (d->history_cap < 0) return fail(CHASM_EINVAL, "history_cap must be >= 0");
+    if (d->flags & ~(uint32_t)(CHASM_FLAG_REDUCE_EACH_STEP | CHASM_FLAG_GRAPH)) return fail(CHASM_EINVAL, "unknown flags");
+    if (d->nx[0] != d->nx[1] || d->nx[0] != d->nx[2])
+        return fail(CHASM_EUNSUPPORTED, "kernels are built for equal nx on the three axes");
+    if (d->patch[0] != d->patch[1] || d->patch[0] != d->patch[2])
+        return fail(CHASM_EUNSUPPORTED, "kernels are built for equal patch sizes on the three axes");
+    const KernelSet* ks = find_kernels(d->dtype, d->nx[0], d->patch[0], d->ghost);
+    if (!ks) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "no kernel built for dtype=%d nx=%d patch=%d ghost=%d", d->dtype, d->nx[0],
+                      d->patch[0], d->ghost);
+        return fail(CHASM_EUNSUPPORTED, buf);
+    }
+    if (d->schedule == CHASM_SCHED_CUBE && !ks->cube)
+        return fail(CHASM_EUNSUPPORTED, "the x-cube does not fit in LDS for this nx and dtype");
+    const double items = (double)d->nbatch * d->nk[0] * d->nk[1] * d->nk[2];
+    if (items * d->nx[0] > 2.0e9) return fail(CHASM_EUNSUPPORTED, "too many items for one launch grid");
+    if (ks_out) *ks_out = ks;
+    return CHASM_OK;
+}
+
+static int resolve_schedule(const chasm_advect_desc* d, const KernelSet* ks)
+{
+    if (d->schedule != CHASM_SCHED_AUTO) return d->schedule;
+    return ks->cube ? CHASM_SCHED_CUBE : CHASM_SCHED_SLAB;
+}
+
+// Rows of FP64 partials per batch member written by a step's fused reduction.
+static long long step_partial_rows(const chasm_advect_desc* d, const KernelSet* ks, int sched)
+{
+    const long long nkp = (long long)d->nk[0] * d->nk[1] * d->nk[2];
+    return nkp * (sched == CHASM_SCHED_CUBE ? ks->cube_rows : ks->pencil_rows);
+}
+
+struct TableBlock {
+    std::vector<char> bytes;
+    size_t off_f64[3][4];   // stencil, fac, w, (unused) per axis, FP64
+    size_t off_f32[3][4];
+    size_t off_shift[3];
+};
+
+template <typename V>
+static size_t push(std::vector<char>& b, const V* p, size_t n)
+{
+    size_t off = (b.size() + 255) & ~(size_t)255;
+    b.resize(off + n * sizeof(V));
+    std::memcpy(b.data() + off, p, n * sizeof(V));
+    return off;
+}
+
+static bool build_tables(const chasm_advect_desc* d, const KernelSet* ks, TableBlock& tb, std::string& err)
+{
+    AxisTables at[3];
+    for (int a = 0; a < 3; ++a) {
+        const double h = (d->x_hi[a] - d->x_lo[a]) / d->nx[a];
+        const double hk = (d->k_hi[a] - d->k_lo[a]) / d->nk[a];
+        if (!build_axis_tables(d->nx[a], d->patch[a], d->ghost, ks->G, h, d->closure, d->nk[a], d->k_lo[a], hk, d->dt,
+                               at[a], err))
+            return false;
+    }
+    for (int a = 0; a < 3; ++a) {
+        tb.off_f64[a][0] = push(tb.bytes, at[a].stencil.data(), at[a].stencil.size());
+        tb.off_f64[a][1] = push(tb.bytes, at[a].fac.data(), at[a].fac.size());
+        tb.off_f64[a][2] = push(tb.bytes, at[a].w.data(), at[a].w.size());
+        std::vector<float> s32(at[a].stencil.begin(), at[a].stencil.end());
+        std::vector<float> f32(at[a].fac.begin(), at[a].fac.end());
+        std::vector<float> w32(at[a].w.begin(), at[a].w.end());
+        tb.off_f32[a][0] = push(tb.bytes, s32.data(), s32.size());
+        tb.off_f32[a][1] = push(tb.bytes, f32.data(), f32.size());
+        tb.off_f32[a][2] = push(tb.bytes, w32.data(), w32.size());
+        tb.off_shift[a] = push(tb.bytes, at[a].shift.data(), at[a].shift.size());
+    }
+    return true;
+}
+
+static size_t workspace_bytes(const chasm_advect_desc* d, const KernelSet* ks, int sched, size_t table_bytes)
+{
+    const long long nkp = (long long)d->nk[0] * d->nk[1] * d->nk[2];
+    const long long rows = std::max(step_partial_rows(d, ks, sched), nkp) * d->nbatch;
+    const int cap = d->history_cap > 0 ? d->history_cap : 1024;
+    size_t b = table_bytes + 256;
+    b += (size_t)rows * NRED * sizeof(double) + 256;
+    b += (size_t)d->nbatch * NRED * sizeof(double) + 256;
+    if (d->flags & CHASM_FLAG_REDUCE_EACH_STEP) b += (size_t)cap * d->nbatch * NRED * sizeof(double) + 256 + 256;
+    return b;
+}
+
+// Issue one step's kernels on stream s.
+static hipError_t issue_step(chasm_advect_t h, hipStream_t s)
+{
+    const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
+    double* part = red ? h->partials : nullptr;
+    hipError_t e = hipSuccess;
+    switch (h->schedule) {
+    case CHASM_SCHED_CUBE:
+        e = h->ks->cube(h->job, part, s);
+        break;
+    case CHASM_SCHED_SLAB:
+        e = h->ks->slab_x1x2(h->job, nullptr, s);
+        if (e == hipSuccess) e = h->ks->pencil_x3(h->job, part, s);
+        break;
+    default:
+        e = h->ks->slab_x1(h->job, nullptr, s);
+        if (e == hipSuccess) e = h->ks->pencil_x2(h->job, nullptr, s);
+        if (e == hipSuccess) e = h->ks->pencil_x3(h->job, part, s);
+        break;
+    }
+    if (e == hipSuccess && red) {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, h->partials, h->partial_rows, h->fin, h->last, h->hist,
+                           h->counter, h->hist_cap, h->desc.nbatch);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+extern "C" {
+
+const char* chasm_advect_last_error(void) { return g_err.c_str(); }
+
+const char* chasm_advect_version(void) { return "chasm-advect 0.1 (gfx950)"; }
+
+chasm_status chasm_advect_workspace_bytes(const chasm_advect_desc* desc, size_t* bytes)
+{
+    const KernelSet* ks = nullptr;
+    chasm_status st = validate(desc, &ks);
+    if (st != CHASM_OK) return st;
+    if (!bytes) return fail(CHASM_EINVAL, "bytes is NULL");
+    TableBlock tb;
+    std::string err;
+    if (!build_tables(desc, ks, tb, err)) return fail(CHASM_EINVAL, err);
+    *bytes = workspace_bytes(desc, ks, resolve_schedule(desc, ks), tb.bytes.size());
+    return CHASM_OK;
+}
+
+chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, void* hip_stream, chasm_advect_t* out)
+{
+    if (!out) return fail(CHASM_EINVAL, "out is NULL");
+    *out = nullptr;
+    const KernelSet* ks = nullptr;
+    chasm_status st = validate(desc, &ks);
+    if (st != CHASM_OK) return st;
+    if (!f_dev) return fail(CHASM_EINVAL, "f_dev is NULL");
+    if (((uintptr_t)f_dev) % 16) return fail(CHASM_EINVAL, "f_dev must be 16-byte aligned");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, f_dev) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(CHASM_EINVAL, "f_dev is not a device pointer");
+    }
+
+    TableBlock tb;
+    std::string err;
+    if (!build_tables(desc, ks, tb, err)) return fail(CHASM_EINVAL, err);
+
+    chasm_advect_s* h = new (std::nothrow) chasm_advect_s();
+    if (!h) return fail(CHASM_ENOMEM, "host allocation failed");
+    h->desc = *desc;
+    h->f = f_dev;
+    h->stream = (hipStream_t)hip_stream;
+    h->ks = ks;
+    h->schedule = resolve_schedule(desc, ks);
+    hipGetDevice(&h->device);
+
+    auto bail = [&](chasm_status s, const std::string& m) {
+        chasm_advect_destroy(h);
+        return fail(s, m);
+    };
+    hipError_t e = hipMalloc(&h->tables, tb.bytes.size());
+    if (e != hipSuccess) return bail(CHASM_ENOMEM, "hipMalloc(tables) failed");
+    e = hipMemcpyAsync(h->tables, tb.bytes.data(), tb.bytes.size(), hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return bail(CHASM_EDEVICE, "table upload failed");
+
+    const long long nkp = (long long)desc->nk[0] * desc->nk[1] * desc->nk[2];
+    h->partial_rows = step_partial_rows(desc, ks, h->schedule);
+    const long long rows = std::max(h->partial_rows, nkp) * desc->nbatch;
+    if (hipMalloc((void**)&h->partials, (size_t)rows * NRED * sizeof(double)) != hipSuccess)
+        return bail(CHASM_ENOMEM, "hipMalloc(partials) failed");
+    if (hipMalloc((void**)&h->last, (size_t)desc->nbatch * NRED * sizeof(double)) != hipSuccess)
+        return bail(CHASM_ENOMEM, "hipMalloc(diagnostics) failed");
+    if (desc->flags & CHASM_FLAG_REDUCE_EACH_STEP) {
+        h->hist_cap = desc->history_cap > 0 ? desc->history_cap : 1024;
+        if (hipMalloc((void**)&h->hist, (size_t)h->hist_cap * desc->nbatch * NRED * sizeof(double)) != hipSuccess)
+            return bail(CHASM_ENOMEM, "hipMalloc(history) failed");
+        if (hipMalloc((void**)&h->counter, sizeof(int)) != hipSuccess)
+            return bail(CHASM_ENOMEM, "hipMalloc(counter) failed");
+        if (hipMemsetAsync(h->counter, 0, sizeof(int), h->stream) != hipSuccess)
+            return bail(CHASM_EDEVICE, "counter reset failed");
+    }
+
+    const bool f64 = desc->dtype == CHASM_F64;
+    char* tbase = static_cast<char*>(h->tables);
+    h->job.f = f_dev;
+    h->job.nitems = nkp * desc->nbatch;
+    for (int a = 0; a < 3; ++a) {
+        h->job.nk[a] = desc->nk[a];
+        const size_t* off = f64 ? tb.off_f64[a] : tb.off_f32[a];
+        h->job.ax[a].stencil = tbase + off[0];
+        h->job.ax[a].fac = tbase + off[1];
+        h->job.ax[a].w = tbase + off[2];
+        h->job.ax[a].shift = reinterpret_cast<const int*>(tbase + tb.off_shift[a]);
+        const double hx = (desc->x_hi[a] - desc->x_lo[a]) / desc->nx[a];
+        h->job.ax[a].h3 = hx / 3.0;
+        h->job.ax[a].twoh = 2.0 * hx;
+        h->fin.xlo[a] = desc->x_lo[a];
+        h->fin.hx[a] = hx;
+        h->fin.klo[a] = desc->k_lo[a];
+        h->fin.hk[a] = (desc->k_hi[a] - desc->k_lo[a]) / desc->nk[a];
+    }
+    h->job.ghost = desc->closure == CHASM_CLOSURE_POLY3 ? 1.0 : 0.0;
+    h->fin.vol = h->fin.hx[0] * h->fin.hx[1] * h->fin.hx[2] * h->fin.hk[0] * h->fin.hk[1] * h->fin.hk[2];
+
+    if (desc->flags & CHASM_FLAG_GRAPH) {
+        if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(CHASM_EDEVICE, "capture stream creation failed");
+        if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return bail(CHASM_EDEVICE, "hipStreamBeginCapture failed");
+        hipError_t ce = issue_step(h, h->cap_stream);
+        hipError_t ee = hipStreamEndCapture(h->cap_stream, &h->graph);
+        if (ce != hipSuccess || ee != hipSuccess) return bail(CHASM_EDEVICE, "step capture failed");
+        if (hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0) != hipSuccess)
+            return bail(CHASM_EDEVICE, "hipGraphInstantiate failed");
+    }
+    *out = h;
+    return CHASM_OK;
+}
+
+chasm_status chasm_advect_step(chasm_advect_t h, int32_t nsteps)
+{
+    if (!h) return fail(CHASM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
+    if (nsteps < 0) return fail(CHASM_EINVAL, "nsteps must be >= 0");
+    for (int32_t s = 0; s < nsteps; ++s) {
+        hipError_t e = h->gexec ? hipGraphLaunch(h->gexec, h->stream) : issue_step(h, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "step launch");
+    }
+    return CHASM_OK;
+}
+
+chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const int32_t* nsteps)
+{
+    if (n < 0 || (n > 0 && (!hs || !nsteps))) return fail(CHASM_EINVAL, "bad handle list");
+    int32_t most = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!hs[i]) return fail(CHASM_EINVAL, "NULL handle in list");
+        if (hs[i]->poisoned) return fail(CHASM_ESTATE, "a handle in the list is poisoned");
+        if (nsteps[i] < 0) return fail(CHASM_EINVAL, "nsteps must be >= 0");
+        if (hs[i]->stream != hs[0]->stream) return fail(CHASM_EINVAL, "all handles must share one stream");
+        most = std::max(most, nsteps[i]);
+    }
+    // Step-major order: every job advances one step before any job takes the next.
+    for (int32_t s = 0; s < most; ++s)
+        for (int32_t i = 0; i < n; ++i) {
+            if (s >= nsteps[i]) continue;
+            chasm_advect_t h = hs[i];
+            hipError_t e = h->gexec ? hipGraphLaunch(h->gexec, h->stream) : issue_step(h, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "step launch");
+        }
+    return CHASM_OK;
+}
+
+chasm_status chasm_advect_diagnostics(chasm_advect_t h, double* out)
+{
+    if (!h || !out) return fail(CHASM_EINVAL, "NULL argument");
+    if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
+    hipError_t e = h->ks->reduce(h->job, h->partials, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "reduce launch");
+    const long long nkp = (long long)h->desc.nk[0] * h->desc.nk[1] * h->desc.nk[2];
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->partials, nkp, h->fin, h->last,
+                       (double*)nullptr, (int*)nullptr, 1, h->desc.nbatch);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "finalize launch");
+    e = hipMemcpyAsync(out, h->last, (size_t)h->desc.nbatch * NRED * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "diagnostics copy");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+    return CHASM_OK;
+}
+
+chasm_status chasm_advect_mass(chasm_advect_t h, double* mass, double* l2, double* moments6)
+{
+    if (!h || !mass) return fail(CHASM_EINVAL, "NULL argument");
+    std::vector<double> all((size_t)h->desc.nbatch * NRED);
+    chasm_status st = chasm_advect_diagnostics(h, all.data());
+    if (st != CHASM_OK) return st;
+    double s[NRED] = {0};
+    for (int b = 0; b < h->desc.nbatch; ++b)
+        for (int v = 0; v < NRED; ++v) s[v] += all[(size_t)b * NRED + v];
+    *mass = s[0];
+    if (l2) *l2 = s[1];
+    if (moments6)
+        for (int v = 0; v < 6; ++v) moments6[v] = s[2 + v];
+    return CHASM_OK;
+}
+
+chasm_status chasm_advect_history(chasm_advect_t h, double* out, int32_t max_steps, int32_t* n_out)
+{
+    if (!h || !n_out || (max_steps > 0 && !out)) return fail(CHASM_EINVAL, "NULL argument");
+    if (max_steps < 0) return fail(CHASM_EINVAL, "max_steps must be >= 0");
+    if (!h->hist) return fail(CHASM_EINVAL, "handle was created without CHASM_FLAG_REDUCE_EACH_STEP");
+    if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
+    int count = 0;
+    hipError_t e = hipMemcpyAsync(&count, h->counter, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "history counter read");
+    const int avail = std::min(count, h->hist_cap);
+    const int n = std::min(avail, (int)max_steps);
+    const size_t row = (size_t)h->desc.nbatch * NRED;
+    std::vector<double> ring((size_t)h->hist_cap * row);
+    e = hipMemcpy(ring.data(), h->hist, ring.size() * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "history copy");
+    // oldest kept entry is step count - avail; return the first n of the kept ones
+    for (int i = 0; i < n; ++i) {
+        const int step = count - avail + i;
+        std::memcpy(out + (size_t)i * row, ring.data() + (size_t)(step % h->hist_cap) * row, row * sizeof(double));
+    }
+    *n_out = n;
+    return CHASM_OK;
+}
+
+chasm_status chasm_advect_schedule(chasm_advect_t h, int32_t* schedule)
+{
+    if (!h || !schedule) return fail(CHASM_EINVAL, "NULL argument");
+    *schedule = h->schedule;
+    return CHASM_OK;
+}
+
+chasm_status chasm_advect_destroy(chasm_advect_t h)
+{
+    if (!h) return CHASM_OK;
+    hipError_t e = hipSuccess;
+    if (h->stream || h->tables) e = hipStreamSynchronize(h->stream);
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    if (h->graph) hipGraphDestroy(h->graph);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    if (h->tables) hipFree(h->tables);
+    if (h->partials) hipFree(h->partials);
+    if (h->last) hipFree(h->last);
+    if (h->hist) hipFree(h->hist);
+    if (h->counter) hipFree(h->counter);
+    delete h;
+    if (e != hipSuccess) return fail(CHASM_EDEVICE, std::string("destroy: ") + hipGetErrorString(e));
+    return CHASM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,422 @@
+// chasm_kernels.hpp -- gfx950 kernels of the characteristic (spatial-advection)
+// step of the CHASM scheme (arXiv:2205.02380, Sec. 3), f(x,k) <- f(x - k dt, k).
+//
+// Field layout: f[b][k3][k2][k1][x3][x2][x1], x1 fastest; one "item" is the x-cube of
+// one (b, k) pair (N^3 contiguous values).  The three axis sweeps of a step
+// (eqs. 3.11-3.12 factored axis by axis, order x1, x2, x3) are independent per item,
+// because the shift alpha_d = k_d dt / h_d depends on k only.
+//
+// Kernels (each reads and writes f once per launch, in place):
+//   k_cube    all three sweeps of one item with the whole x-cube in LDS
+//             (N^2 (N+1) values, rows padded to N+1 so x1-, x2- and x3-lines are
+//             bank-conflict free): 8 B/point-update in FP32.
+//   k_slab    x1 sweep, optionally followed by the x2 sweep, on S x3-slabs (N x N)
+//             held in LDS.
+//   k_pencil  x2 or x3 sweep; each lane holds one whole line in VGPRs, lanes of a
+//             wave hold neighbouring x1 columns, so every load and store of the
+//             wave is a contiguous run of x1.
+//   k_reduce_field, k_finalize: FP64 diagnostics (mass, L2, first moments).
+// Reductions can be fused into the last sweep of a step; every block writes its
+// own FP64 partials and k_finalize sums them in a fixed order (deterministic).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "chasm_line.hpp"
+
+namespace chasm {
+
+struct AxisTabDev {
+    const void* stencil;   // T[(P+1)][2G+1]
+    const void* fac;       // T[2][3][M+1]
+    const int* shift;      // int[nk]   sigma = floor(-alpha(k))
+    const void* w;         // T[nk][4]  shift weights
+    double h3, twoh;
+};
+
+struct JobDev {
+    void* f;               // field base (caller-owned device memory)
+    long long nitems;      // nbatch * nk1 * nk2 * nk3
+    int nk[3];
+    double ghost;          // 0 paper closure, 1 cubic-exact closure
+    AxisTabDev ax[3];
+};
+
+// Number of FP64 partials written per block when reducing.
+constexpr int NRED = 8;
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+template <>
+struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+
+template <typename T>
+__device__ __forceinline__ T vget(const typename Vec16<T>::type& v, int i);
+template <>
+__device__ __forceinline__ float vget<float>(const float4& v, int i)
+{
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+template <>
+__device__ __forceinline__ double vget<double>(const double2& v, int i) { return i == 0 ? v.x : v.y; }
+
+template <typename T>
+__device__ __forceinline__ void vset(typename Vec16<T>::type& v, int i, T x);
+template <>
+__device__ __forceinline__ void vset<float>(float4& v, int i, float x)
+{
+    if (i == 0) v.x = x; else if (i == 1) v.y = x; else if (i == 2) v.z = x; else v.w = x;
+}
+template <>
+__device__ __forceinline__ void vset<double>(double2& v, int i, double x)
+{
+    if (i == 0) v.x = x; else v.y = x;
+}
+
+// Raw buffer access: a per-wave resource over [base, base + bytes), a per-lane byte
+// offset (VGPR) and a uniform byte offset (SGPR), so a strided line needs no
+// per-element 64-bit address registers.  Out-of-range accesses load 0 and drop
+// stores (hardware range check against the resource size).
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ Buf(const void* base, uint32_t bytes)
+        : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000))
+    {
+    }
+    template <typename T>
+    __device__ __forceinline__ T load(uint32_t voff, uint32_t soff) const
+    {
+        if constexpr (sizeof(T) == 4) {
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+        } else {
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+        }
+    }
+    template <typename T>
+    __device__ __forceinline__ void store(T x, uint32_t voff, uint32_t soff) const
+    {
+        if constexpr (sizeof(T) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, x), r, (int)voff, (int)soff, 0);
+        } else {
+            using I2 = int __attribute__((ext_vector_type(2)));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(I2, x), r, (int)voff, (int)soff, 0);
+        }
+    }
+};
+
+__device__ __forceinline__ void item_k(const JobDev& job, long long item, int ik[3])
+{
+    const long long nkp = (long long)job.nk[0] * job.nk[1] * job.nk[2];
+    const int kf = (int)(item % nkp);
+    ik[0] = kf % job.nk[0];
+    ik[1] = (kf / job.nk[0]) % job.nk[1];
+    ik[2] = kf / (job.nk[0] * job.nk[1]);
+}
+
+template <typename T>
+__device__ __forceinline__ AxisCoef<T> axis_coef(const JobDev& job, int d, int ik, int& sigma)
+{
+    const AxisTabDev& a = job.ax[d];
+    AxisCoef<T> c;
+    c.stencil = static_cast<const T*>(a.stencil);
+    c.fac = static_cast<const T*>(a.fac);
+    c.h3 = (T)a.h3;
+    c.twoh = (T)a.twoh;
+    const T* w = static_cast<const T*>(a.w) + 4 * ik;
+    c.w0 = w[0];
+    c.w1 = w[1];
+    c.w2 = w[2];
+    c.w3 = w[3];
+    c.ghost = (T)job.ghost;
+    sigma = a.shift[ik];
+    return c;
+}
+
+// Sum NV doubles over the block; thread 0 ends up with the totals in acc.
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum(double (&acc)[NV])
+{
+    __shared__ double red[NT / 64][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double x = acc[v];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+        acc[v] = x;
+    }
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    if (NT > 64) {
+        if (ln == 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) red[wv][v] = acc[v];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double s = 0.0;
+                for (int w = 0; w < NT / 64; ++w) s += red[w][v];
+                acc[v] = s;
+            }
+        }
+    }
+}
+
+// Block partials: [sum f, sum f^2, sum i1 f, sum i2 f, sum i3 f, sum ik1 f, sum ik2 f, sum ik3 f].
+template <int NT>
+__device__ __forceinline__ void write_partials(double (&acc)[5], const int ik[3], double* __restrict__ out)
+{
+    block_sum<NT, 5>(acc);
+    if (threadIdx.x == 0) {
+        out[0] = acc[0];
+        out[1] = acc[1];
+        out[2] = acc[2];
+        out[3] = acc[3];
+        out[4] = acc[4];
+        out[5] = ik[0] * acc[0];
+        out[6] = ik[1] * acc[0];
+        out[7] = ik[2] * acc[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Whole x-cube in LDS: x1, x2 and x3 sweeps of one item per block.
+template <typename T, int N, int M, int G, int NT>
+__global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ partials)
+{
+    constexpr int PX = N + 1;
+    constexpr int VW = Vec16<T>::n;
+    static_assert(N % VW == 0, "row length must be a multiple of the vector width");
+    using V = typename Vec16<T>::type;
+    __shared__ T lds[N * N * PX];
+
+    const long long item = blockIdx.x;
+    int ik[3];
+    item_k(job, item, ik);
+    T* __restrict__ cube = static_cast<T*>(job.f) + item * (long long)(N * N * N);
+
+    const V* __restrict__ src = reinterpret_cast<const V*>(cube);
+#pragma unroll 4
+    for (int e = threadIdx.x; e < N * N * N / VW; e += NT) {
+        const V x = src[e];
+        const int row = (e * VW) / N, x1 = (e * VW) % N;
+#pragma unroll
+        for (int i = 0; i < VW; ++i) lds[row * PX + x1 + i] = vget<T>(x, i);
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int sigma;
+        const AxisCoef<T> kc = axis_coef<T>(job, d, ik[d], sigma);
+#pragma unroll 1
+        for (int l = threadIdx.x; l < N * N; l += NT) {
+            int base, stride;
+            if (d == 0) { base = l * PX; stride = 1; }                               // (x2, x3) = (l%N, l/N)
+            else if (d == 1) { base = (l / N) * N * PX + (l % N); stride = PX; }     // (x1, x3)
+            else { base = (l / N) * PX + (l % N); stride = N * PX; }                // (x1, x2)
+            T v[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = lds[base + i * stride];
+            T cv[N + 7];
+            line_cells<T, N, M, G>(v, cv, kc);
+            store_shifted<T, N>(cv, sigma, [&](int j, T x) { lds[base + j * stride] = x; });
+        }
+        __syncthreads();
+    }
+
+    V* __restrict__ dst = reinterpret_cast<V*>(cube);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int e = threadIdx.x; e < N * N * N / VW; e += NT) {
+        const int row = (e * VW) / N, x1 = (e * VW) % N;
+        V x;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < VW; ++i) {
+            const T y = lds[row * PX + x1 + i];
+            vset<T>(x, i, y);
+            if (partials) {
+                const double yd = (double)y;
+                s += yd;
+                acc[1] = fma(yd, yd, acc[1]);
+                acc[2] = fma((double)(x1 + i), yd, acc[2]);
+            }
+        }
+        dst[e] = x;
+        if (partials) {
+            acc[0] += s;
+            acc[3] = fma((double)(row % N), s, acc[3]);
+            acc[4] = fma((double)(row / N), s, acc[4]);
+        }
+    }
+    if (partials) write_partials<NT>(acc, ik, partials + item * NRED);
+}
+
+// ---------------------------------------------------------------------------
+// S x3-slabs (N x N each) per block in LDS: x1 sweep, then (X2 = true) the x2 sweep
+// stored straight to global memory.  Block = S*N threads, one line each.
+template <typename T, int N, int M, int G, int S, bool X2>
+__global__ __launch_bounds__(S * N) void k_slab(JobDev job)
+{
+    constexpr int PX = N + 1;
+    constexpr int NT = S * N;
+    constexpr int VW = Vec16<T>::n;
+    static_assert(N % VW == 0 && N % S == 0, "bad slab shape");
+    using V = typename Vec16<T>::type;
+    __shared__ T lds[S * N * PX];
+
+    constexpr int BPI = N / S;                     // blocks per item
+    const long long item = blockIdx.x / BPI;
+    const int slab0 = (blockIdx.x % BPI) * S;
+    int ik[3];
+    item_k(job, item, ik);
+    T* __restrict__ base_ptr = static_cast<T*>(job.f) + item * (long long)(N * N * N) + (long long)slab0 * N * N;
+
+    const V* __restrict__ src = reinterpret_cast<const V*>(base_ptr);
+#pragma unroll
+    for (int e = threadIdx.x; e < S * N * N / VW; e += NT) {
+        const V x = src[e];
+        const int row = (e * VW) / N, x1 = (e * VW) % N;
+#pragma unroll
+        for (int i = 0; i < VW; ++i) lds[row * PX + x1 + i] = vget<T>(x, i);
+    }
+    __syncthreads();
+
+    {
+        int sigma;
+        const AxisCoef<T> kc = axis_coef<T>(job, 0, ik[0], sigma);
+        const int base = threadIdx.x * PX;          // row (x2, slab) = (t % N, t / N)
+        T v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = lds[base + i];
+        T cv[N + 7];
+        line_cells<T, N, M, G>(v, cv, kc);
+        store_shifted<T, N>(cv, sigma, [&](int j, T x) { lds[base + j] = x; });
+    }
+    __syncthreads();
+
+    if (!X2) {
+        V* __restrict__ dst = reinterpret_cast<V*>(base_ptr);
+#pragma unroll
+        for (int e = threadIdx.x; e < S * N * N / VW; e += NT) {
+            const int row = (e * VW) / N, x1 = (e * VW) % N;
+            V x;
+#pragma unroll
+            for (int i = 0; i < VW; ++i) vset<T>(x, i, lds[row * PX + x1 + i]);
+            dst[e] = x;
+        }
+    } else {
+        int sigma;
+        const AxisCoef<T> kc = axis_coef<T>(job, 1, ik[1], sigma);
+        const int slab = threadIdx.x / N, col = threadIdx.x % N;
+        const int base = slab * N * PX + col;
+        T v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
+        T cv[N + 7];
+        line_cells<T, N, M, G>(v, cv, kc);
+        T* __restrict__ out = base_ptr + slab * N * N + col;
+        store_shifted<T, N>(cv, sigma, [&](int j, T x) { out[j * N] = x; });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One line per lane along axis AXIS (1: x2, 2: x3), NT lines per block; NT divides
+// N*N so a block never straddles two items.  Optional fused FP64 partials.
+template <typename T, int N, int M, int G, int NT, int AXIS>
+__global__ __launch_bounds__(NT) void k_pencil(JobDev job, double* __restrict__ partials)
+{
+    static_assert((N * N) % NT == 0, "block must tile the lines of one item");
+    constexpr int BPI = N * N / NT;
+    const long long item = blockIdx.x / BPI;
+    const int L = (blockIdx.x % BPI) * NT + threadIdx.x;
+    int ik[3];
+    item_k(job, item, ik);
+    T* __restrict__ cube = static_cast<T*>(job.f) + item * (long long)(N * N * N);
+
+    // o1, o2: indices of the two other axes (x1 and x2 for AXIS 2, x1 and x3 for AXIS 1)
+    const int o1 = L % N, o2 = L / N;
+    const int base = AXIS == 2 ? L : o2 * N * N + o1;
+
+    int sigma;
+    const AxisCoef<T> kc = axis_coef<T>(job, AXIS, ik[AXIS], sigma);
+    const Buf buf(cube, (uint32_t)(N * N * N * sizeof(T)));
+    const uint32_t voff = (uint32_t)base * sizeof(T);
+    constexpr uint32_t sstride = (uint32_t)((AXIS == 2 ? N * N : N) * sizeof(T));
+    T v[N];
+    static_for<0, N>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        v[i] = buf.load<T>(voff, i * sstride);
+    });
+    T cv[N + 7];
+    line_cells<T, N, M, G>(v, cv, kc);
+    if (!partials) {
+        store_shifted<T, N>(cv, sigma, [&](int j, T x) { buf.store<T>(x, voff, j * sstride); });
+    } else {
+        double s = 0.0, s2 = 0.0, sj = 0.0;
+        store_shifted<T, N>(cv, sigma, [&](int j, T x) {
+            buf.store<T>(x, voff, j * sstride);
+            const double y = (double)x;
+            s += y;
+            s2 = fma(y, y, s2);
+            sj = fma((double)j, y, sj);
+        });
+        double acc[5];
+        acc[0] = s;
+        acc[1] = s2;
+        acc[2] = (double)o1 * s;
+        if (AXIS == 2) { acc[3] = (double)o2 * s; acc[4] = sj; }
+        else { acc[3] = sj; acc[4] = (double)o2 * s; }
+        write_partials<NT>(acc, ik, partials + (long long)blockIdx.x * NRED);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics of the current field, one item per block.
+template <typename T, int N, int NT>
+__global__ __launch_bounds__(NT) void k_reduce_field(JobDev job, double* __restrict__ partials)
+{
+    constexpr int VW = Vec16<T>::n;
+    using V = typename Vec16<T>::type;
+    const long long item = blockIdx.x;
+    int ik[3];
+    item_k(job, item, ik);
+    const V* __restrict__ src = reinterpret_cast<const V*>(static_cast<const T*>(job.f) + item * (long long)(N * N * N));
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = threadIdx.x; e < N * N * N / VW; e += NT) {
+        const V x = src[e];
+        const int row = (e * VW) / N, x1 = (e * VW) % N;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < VW; ++i) {
+            const double y = (double)vget<T>(x, i);
+            s += y;
+            acc[1] = fma(y, y, acc[1]);
+            acc[2] = fma((double)(x1 + i), y, acc[2]);
+        }
+        acc[0] += s;
+        acc[3] = fma((double)(row % N), s, acc[3]);
+        acc[4] = fma((double)(row / N), s, acc[4]);
+    }
+    write_partials<NT>(acc, ik, partials + item * NRED);
+}
+
+struct FinalizeArgs {
+    double xlo[3], hx[3], klo[3], hk[3];
+    double vol;
+};
+
+// Sum the partials of each batch member in a fixed order and convert index moments
+// to physical ones.  Block b handles batch member b: partial rows
+// [b*rows_per_batch, (b+1)*rows_per_batch).  Results go to out[b*8 .. b*8+7]; when
+// hist is non-null they are also appended at history slot *counter (incremented by
+// block 0 after all blocks have read it -- one launch, so the read happens first).
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, long long rows_per_batch,
+                                                  FinalizeArgs a, double* __restrict__ out,
+                                                  double* __restrict__ hist, int* __restrict__ counter,
+                                                  int hist_cap, int nbatch);
+
+}  // namespace chasm

@@ -1,0 +1,89 @@
+// chasm_launch.hpp -- launch shapes and launchers of the kernel templates.
+// Included only by the instantiation units (inst_n*.hip).
+#pragma once
+#include "chasm_kernels.hpp"
+#include "chasm_registry.hpp"
+
+namespace chasm {
+
+// LDS available to one work-group on gfx950.
+constexpr size_t kLdsBytes = 160 * 1024;
+
+template <typename T, int N>
+struct Launch {
+    // Whole x-cube in LDS (rows padded to N+1) plus the block-sum scratch.
+    static constexpr bool cube_fits = (size_t)N * N * (N + 1) * sizeof(T) + 1024 <= kLdsBytes;
+    static constexpr int cube_nt = N <= 8 ? 64 : (N <= 16 ? 256 : (N <= 24 ? 192 : 512));
+    // x3-slabs per slab block: S*N threads, a multiple of 64, S | N.
+    static constexpr int slab_s = N == 8 ? 8 : (N == 16 ? 4 : (N == 24 ? 8 : (N == 32 ? 2 : (N == 48 ? 4 : 1))));
+    // lines per pencil block: a multiple of 64 dividing N*N.
+    static constexpr int pencil_nt = N == 8 ? 64 : (N == 24 ? 192 : 256);
+    static constexpr int reduce_nt = 256;
+};
+
+template <typename T, int N, int M, int G>
+hipError_t launch_cube(const JobDev& job, double* partials, hipStream_t s)
+{
+    using Lc = Launch<T, N>;
+    if constexpr (Lc::cube_fits) {
+        hipLaunchKernelGGL((k_cube<T, N, M, G, Lc::cube_nt>), dim3((unsigned)job.nitems), dim3(Lc::cube_nt), 0, s, job,
+                           partials);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidConfiguration;
+    }
+}
+
+template <typename T, int N, int M, int G, bool X2>
+hipError_t launch_slab(const JobDev& job, double*, hipStream_t s)
+{
+    using Lc = Launch<T, N>;
+    constexpr int S = Lc::slab_s;
+    const unsigned grid = (unsigned)(job.nitems * (N / S));
+    hipLaunchKernelGGL((k_slab<T, N, M, G, S, X2>), dim3(grid), dim3(S * N), 0, s, job);
+    return hipGetLastError();
+}
+
+template <typename T, int N, int M, int G, int AXIS>
+hipError_t launch_pencil(const JobDev& job, double* partials, hipStream_t s)
+{
+    using Lc = Launch<T, N>;
+    constexpr int NT = Lc::pencil_nt;
+    const unsigned grid = (unsigned)(job.nitems * (N * N / NT));
+    hipLaunchKernelGGL((k_pencil<T, N, M, G, NT, AXIS>), dim3(grid), dim3(NT), 0, s, job, partials);
+    return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t launch_reduce(const JobDev& job, double* partials, hipStream_t s)
+{
+    using Lc = Launch<T, N>;
+    hipLaunchKernelGGL((k_reduce_field<T, N, Lc::reduce_nt>), dim3((unsigned)job.nitems), dim3(Lc::reduce_nt), 0, s,
+                       job, partials);
+    return hipGetLastError();
+}
+
+template <typename T, int N, int M, int G>
+const KernelSet* kernel_set()
+{
+    using Lc = Launch<T, N>;
+    static const KernelSet ks = {
+        sizeof(T) == 8 ? 1 : 0,
+        N,
+        M,
+        G,
+        Lc::cube_fits ? &launch_cube<T, N, M, G> : nullptr,
+        &launch_slab<T, N, M, G, false>,
+        &launch_slab<T, N, M, G, true>,
+        &launch_pencil<T, N, M, G, 1>,
+        &launch_pencil<T, N, M, G, 2>,
+        &launch_reduce<T, N>,
+        1,
+        N * N / Lc::pencil_nt,
+    };
+    return &ks;
+}
+
+#define CHASM_INSTANTIATE(T, N, M, G) template const KernelSet* kernel_set<T, N, M, G>();
+
+}  // namespace chasm

@@ -1,0 +1,37 @@
+// chasm_tables.hpp -- host-side FP64 tables of one axis of the advection step.
+//
+// For an axis of N nodes with patches of M cells, ghost width g, spacing h:
+//   stencil  (P+1) rows of width 2G+1: interface slopes d_q = sum_t S[q][t] phi[I_q-G+t]
+//            (PMBC, eqs. 3.4-3.5; rows of the natural-BC inverse, truncated to
+//            |j - I_q| <= g; G >= g is the kernel's compile-time window)
+//   fac      Thomas factors of the reduced patch system for m = M (slot 0) and
+//            m = MLAST (slot 1): inv[i], a_i*inv[i], c'[i] (Sec. 3.1.2 step 5)
+//   shift/w  per k node: sigma = floor(-alpha), alpha = k dt / h, and the weights
+//            w_r = b_{4-r}(1 - beta) of eq. 3.8, beta = -alpha - sigma.
+#pragma once
+#include <string>
+#include <vector>
+
+namespace chasm {
+
+struct AxisTables {
+    int N = 0, M = 0, P = 0, MLAST = 0, g = 0, G = 0;
+    double h = 0.0;
+    std::vector<double> stencil;   // (P+1)*(2G+1)
+    std::vector<double> fac;       // 2*3*(M+1)
+    std::vector<int> shift;        // nk
+    std::vector<double> w;         // nk*4
+};
+
+// Number of patches of M cells covering N nodes.
+inline int npatch(int N, int M) { return (N - 1 + M - 1) / M; }
+
+// Slopes s'(x_I) of the natural cubic spline of the data, as rows over the data:
+// out[(N)*q + j] for each requested interface I_q.  Returns false on bad input.
+bool natural_slope_rows(int N, double h, const std::vector<int>& ifaces, std::vector<double>& out);
+
+// Build every table of one axis.  closure: 0 paper PMBC, 1 cubic-exact variant.
+bool build_axis_tables(int N, int M, int g, int G, double h, int closure, int nk, double k_lo, double hk,
+                       double dt, AxisTables& out, std::string& err);
+
+}  // namespace chasm

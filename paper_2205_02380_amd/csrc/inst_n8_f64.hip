@@ -1,0 +1,6 @@
+// Kernel instantiations: CHASM_SHAPES_N8_F64.
+#include "chasm_launch.hpp"
+
+namespace chasm {
+CHASM_SHAPES_N8_F64(CHASM_INSTANTIATE)
+}  // namespace chasm

@@ -244,3 +244,15 @@ def serving_trace(n: int = 200, rate: float = 20.0, seed: int = 5,
     dt_i = rng.integers(0, len(dts), size=n)
     return [Request(i, float(t[i]), shapes[int(shape_i[i])], int(steps[i]), float(dts[int(dt_i[i])]),
                     random_packets(4, 5000 + i)) for i in range(n)]
+
+
+def gaussian_cubes(grid: Grid, pk: Packets, kidx) -> np.ndarray:
+    """FP64 x-cubes of f0 at the k-points kidx[n] = (i1, i2, i3): array [n][x3][x2][x1]."""
+    coef, gx, gk = packet_factors(grid, pk)
+    kidx = np.asarray(kidx).reshape(-1, 3)
+    out = np.zeros((kidx.shape[0], grid.nx[2], grid.nx[1], grid.nx[0]))
+    for p in range(pk.n):
+        cube = gx[p][2][:, None, None] * gx[p][1][None, :, None] * gx[p][0][None, None, :]
+        for n, (i1, i2, i3) in enumerate(kidx):
+            out[n] += coef[p] * gk[p][0][i1] * gk[p][1][i2] * gk[p][2][i3] * cube
+    return out

@@ -95,6 +95,18 @@ struct Buf {
         }
     }
     template <typename T>
+    __device__ __forceinline__ typename Vec16<T>::type load16(uint32_t voff, uint32_t soff) const
+    {
+        return __builtin_bit_cast(typename Vec16<T>::type,
+                                  __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+    }
+    template <typename T>
+    __device__ __forceinline__ void store16(const typename Vec16<T>::type& x, uint32_t voff, uint32_t soff) const
+    {
+        using I4 = int __attribute__((ext_vector_type(4)));
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(I4, x), r, (int)voff, (int)soff, 0);
+    }
+    template <typename T>
     __device__ __forceinline__ void store(T x, uint32_t voff, uint32_t soff) const
     {
         if constexpr (sizeof(T) == 4) {
@@ -115,22 +127,27 @@ __device__ __forceinline__ void item_k(const JobDev& job, long long item, int ik
     ik[2] = kf / (job.nk[0] * job.nk[1]);
 }
 
+// Tables are read-only for the whole kernel: read them through the constant address
+// space, which lets the compiler use scalar loads into SGPRs.
 template <typename T>
-__device__ __forceinline__ AxisCoef<T> axis_coef(const JobDev& job, int d, int ik, int& sigma)
+using cptr = const T __attribute__((address_space(4)))*;
+
+template <typename T>
+__device__ __forceinline__ AxisCoef<T, cptr<T>> axis_coef(const JobDev& job, int d, int ik, int& sigma)
 {
     const AxisTabDev& a = job.ax[d];
-    AxisCoef<T> c;
-    c.stencil = static_cast<const T*>(a.stencil);
-    c.fac = static_cast<const T*>(a.fac);
+    AxisCoef<T, cptr<T>> c;
+    c.stencil = (cptr<T>)(a.stencil);
+    c.fac = (cptr<T>)(a.fac);
     c.h3 = (T)a.h3;
     c.twoh = (T)a.twoh;
-    const T* w = static_cast<const T*>(a.w) + 4 * ik;
+    const cptr<T> w = (cptr<T>)(a.w) + 4 * ik;
     c.w0 = w[0];
     c.w1 = w[1];
     c.w2 = w[2];
     c.w3 = w[3];
     c.ghost = (T)job.ghost;
-    sigma = a.shift[ik];
+    sigma = ((const int __attribute__((address_space(4)))*)(a.shift))[ik];
     return c;
 }
 
@@ -182,77 +199,139 @@ __device__ __forceinline__ void write_partials(double (&acc)[5], const int ik[3]
 }
 
 // ---------------------------------------------------------------------------
-// Whole x-cube in LDS: x1, x2 and x3 sweeps of one item per block.
+// Whole x-cube in LDS: x1, x2 and x3 sweeps of one item at a time.
+//
+// Persistent: each block walks items blockIdx.x, blockIdx.x + gridDim.x, ...  An item
+// enters LDS in rounds of PL = NT/N x3-planes; the x1 and x2 sweeps only couple nodes
+// within a plane, so they run on each round as soon as it lands, while the next
+// round -- or, after the last round, the next item's first round -- is already in
+// flight into VGPRs (N/VW 16-byte buffer loads per lane).  The x3 sweep then runs on
+// the whole cube and the result streams out, with the FP64 partials when asked for.
 template <typename T, int N, int M, int G, int NT>
 __global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ partials)
 {
     constexpr int PX = N + 1;
     constexpr int VW = Vec16<T>::n;
-    static_assert(N % VW == 0, "row length must be a multiple of the vector width");
+    constexpr int PL = NT / N;                    // planes per round
+    constexpr int ROUNDS = N / PL;
+    constexpr int RV = N / VW;                    // 16-byte vectors per lane per round
+    constexpr int NV = N * N * N / VW;            // 16-byte vectors per cube
+    constexpr uint32_t CUBE_BYTES = (uint32_t)(N * N * N * sizeof(T));
+    static_assert(NT % N == 0 && N % PL == 0 && N % VW == 0 && NV % NT == 0, "bad cube tiling");
     using V = typename Vec16<T>::type;
     __shared__ T lds[N * N * PX];
 
-    const long long item = blockIdx.x;
-    int ik[3];
-    item_k(job, item, ik);
-    T* __restrict__ cube = static_cast<T*>(job.f) + item * (long long)(N * N * N);
-
-    const V* __restrict__ src = reinterpret_cast<const V*>(cube);
-#pragma unroll 4
-    for (int e = threadIdx.x; e < N * N * N / VW; e += NT) {
-        const V x = src[e];
-        const int row = (e * VW) / N, x1 = (e * VW) % N;
+    // tid is re-derived inside the item loop through an opaque copy, so per-lane
+    // addresses and coordinates are recomputed per item instead of being hoisted out
+    // of the loop and pinned in registers for its whole length.
+    int tid = (int)threadIdx.x;
+    V pre[RV];
+    auto fetch = [&](long long it, int round) {
+        const uint32_t voff = (uint32_t)tid * 16u;
+        const Buf b(static_cast<const T*>(job.f) + it * (long long)(N * N * N), CUBE_BYTES);
+        static_for<0, RV>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            pre[q] = b.template load16<T>(voff, (uint32_t)((round * RV + q) * NT * 16));
+        });
+    };
+    auto fill = [&](int round) {
+        static_for<0, RV>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int e = (round * RV + q) * NT + tid;                     // vector index in the cube
+            const int row = (e * VW) / N, x1 = (e * VW) % N;
 #pragma unroll
-        for (int i = 0; i < VW; ++i) lds[row * PX + x1 + i] = vget<T>(x, i);
-    }
-    __syncthreads();
+            for (int i = 0; i < VW; ++i) lds[row * PX + x1 + i] = vget<T>(pre[q], i);
+        });
+    };
 
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        int sigma;
-        const AxisCoef<T> kc = axis_coef<T>(job, d, ik[d], sigma);
+    long long item = blockIdx.x;
+    if (item < job.nitems) fetch(item, 0);
+    for (; item < job.nitems; item += gridDim.x) {
+        tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        int ik[3];
+        item_k(job, item, ik);
+        int sig0, sig1;
+        const auto k0 = axis_coef<T>(job, 0, ik[0], sig0);
+        const auto k1 = axis_coef<T>(job, 1, ik[1], sig1);
+        const int plane_t = tid / N, lane_t = tid % N;
+
 #pragma unroll 1
-        for (int l = threadIdx.x; l < N * N; l += NT) {
-            int base, stride;
-            if (d == 0) { base = l * PX; stride = 1; }                               // (x2, x3) = (l%N, l/N)
-            else if (d == 1) { base = (l / N) * N * PX + (l % N); stride = PX; }     // (x1, x3)
-            else { base = (l / N) * PX + (l % N); stride = N * PX; }                // (x1, x2)
-            T v[N];
+        for (int r = 0; r < ROUNDS; ++r) {
+            fill(r);
+            __syncthreads();
+            if (r + 1 < ROUNDS) fetch(item, r + 1);
+            else if (item + gridDim.x < job.nitems) fetch(item + gridDim.x, 0);
+            const int plane = r * PL + plane_t;
+            {   // x1: row (x2 = lane_t) of this thread's plane
+                const int base = (plane * N + lane_t) * PX;
+                dispatch_sigma(sig0, [&](auto sc) {
+                    T v[N];
 #pragma unroll
-            for (int i = 0; i < N; ++i) v[i] = lds[base + i * stride];
-            T cv[N + 7];
-            line_cells<T, N, M, G>(v, cv, kc);
-            store_shifted<T, N>(cv, sigma, [&](int j, T x) { lds[base + j * stride] = x; });
-        }
-        __syncthreads();
-    }
-
-    V* __restrict__ dst = reinterpret_cast<V*>(cube);
-    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int e = threadIdx.x; e < N * N * N / VW; e += NT) {
-        const int row = (e * VW) / N, x1 = (e * VW) % N;
-        V x;
-        double s = 0.0;
+                    for (int i = 0; i < N; ++i) v[i] = lds[base + i];
+                    advect_line<T, N, M, G, decltype(sc)::value>(v, k0, sig0, [&](int j, T x) { lds[base + j] = x; });
+                });
+            }
+            __syncthreads();
+            {   // x2: column (x1 = lane_t) of this thread's plane
+                const int base = plane * N * PX + lane_t;
+                dispatch_sigma(sig1, [&](auto sc) {
+                    T v[N];
 #pragma unroll
-        for (int i = 0; i < VW; ++i) {
-            const T y = lds[row * PX + x1 + i];
-            vset<T>(x, i, y);
-            if (partials) {
-                const double yd = (double)y;
-                s += yd;
-                acc[1] = fma(yd, yd, acc[1]);
-                acc[2] = fma((double)(x1 + i), yd, acc[2]);
+                    for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
+                    advect_line<T, N, M, G, decltype(sc)::value>(v, k1, sig1,
+                                                                   [&](int j, T x) { lds[base + j * PX] = x; });
+                });
             }
         }
-        dst[e] = x;
-        if (partials) {
-            acc[0] += s;
-            acc[3] = fma((double)(row % N), s, acc[3]);
-            acc[4] = fma((double)(row / N), s, acc[4]);
+        __syncthreads();
+        {   // x3 over the whole cube
+            int sig2;
+            const auto k2 = axis_coef<T>(job, 2, ik[2], sig2);
+            dispatch_sigma(sig2, [&](auto sc) {
+                constexpr int SIG = decltype(sc)::value;
+#pragma unroll 1
+                for (int l = tid; l < N * N; l += NT) {
+                    const int base = (l / N) * PX + (l % N);                // (x1, x2)
+                    T v[N];
+#pragma unroll
+                    for (int i = 0; i < N; ++i) v[i] = lds[base + i * N * PX];
+                    advect_line<T, N, M, G, SIG>(v, k2, sig2, [&](int j, T x) { lds[base + j * N * PX] = x; });
+                }
+            });
         }
+        __syncthreads();
+
+        const Buf b(static_cast<T*>(job.f) + item * (long long)(N * N * N), CUBE_BYTES);
+        const uint32_t voff = (uint32_t)tid * 16u;
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        static_for<0, NV / NT>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int e = q * NT + tid;
+            const int row = (e * VW) / N, x1 = (e * VW) % N;
+            V x;
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 0; i < VW; ++i) {
+                const T y = lds[row * PX + x1 + i];
+                vset<T>(x, i, y);
+                if (partials) {
+                    const double yd = (double)y;
+                    sum += yd;
+                    acc[1] = fma(yd, yd, acc[1]);
+                    acc[2] = fma((double)(x1 + i), yd, acc[2]);
+                }
+            }
+            b.template store16<T>(x, voff, (uint32_t)(q * NT * 16));
+            if (partials) {
+                acc[0] += sum;
+                acc[3] = fma((double)(row % N), sum, acc[3]);
+                acc[4] = fma((double)(row / N), sum, acc[4]);
+            }
+        });
+        if (partials) write_partials<NT>(acc, ik, partials + item * NRED);
+        __syncthreads();
     }
-    if (partials) write_partials<NT>(acc, ik, partials + item * NRED);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,14 +366,14 @@ __global__ __launch_bounds__(S * N) void k_slab(JobDev job)
 
     {
         int sigma;
-        const AxisCoef<T> kc = axis_coef<T>(job, 0, ik[0], sigma);
+        const auto kc = axis_coef<T>(job, 0, ik[0], sigma);
         const int base = threadIdx.x * PX;          // row (x2, slab) = (t % N, t / N)
-        T v[N];
+        dispatch_sigma(sigma, [&](auto sc) {
+            T v[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = lds[base + i];
-        T cv[N + 7];
-        line_cells<T, N, M, G>(v, cv, kc);
-        store_shifted<T, N>(cv, sigma, [&](int j, T x) { lds[base + j] = x; });
+            for (int i = 0; i < N; ++i) v[i] = lds[base + i];
+            advect_line<T, N, M, G, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { lds[base + j] = x; });
+        });
     }
     __syncthreads();
 
@@ -310,16 +389,16 @@ __global__ __launch_bounds__(S * N) void k_slab(JobDev job)
         }
     } else {
         int sigma;
-        const AxisCoef<T> kc = axis_coef<T>(job, 1, ik[1], sigma);
+        const auto kc = axis_coef<T>(job, 1, ik[1], sigma);
         const int slab = threadIdx.x / N, col = threadIdx.x % N;
         const int base = slab * N * PX + col;
-        T v[N];
-#pragma unroll
-        for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
-        T cv[N + 7];
-        line_cells<T, N, M, G>(v, cv, kc);
         T* __restrict__ out = base_ptr + slab * N * N + col;
-        store_shifted<T, N>(cv, sigma, [&](int j, T x) { out[j * N] = x; });
+        dispatch_sigma(sigma, [&](auto sc) {
+            T v[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
+            advect_line<T, N, M, G, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { out[j * N] = x; });
+        });
     }
 }
 
@@ -342,7 +421,7 @@ __global__ __launch_bounds__(NT) void k_pencil(JobDev job, double* __restrict__ 
     const int base = AXIS == 2 ? L : o2 * N * N + o1;
 
     int sigma;
-    const AxisCoef<T> kc = axis_coef<T>(job, AXIS, ik[AXIS], sigma);
+    const auto kc = axis_coef<T>(job, AXIS, ik[AXIS], sigma);
     const Buf buf(cube, (uint32_t)(N * N * N * sizeof(T)));
     const uint32_t voff = (uint32_t)base * sizeof(T);
     constexpr uint32_t sstride = (uint32_t)((AXIS == 2 ? N * N : N) * sizeof(T));
@@ -351,19 +430,22 @@ __global__ __launch_bounds__(NT) void k_pencil(JobDev job, double* __restrict__ 
         constexpr int i = decltype(ic)::value;
         v[i] = buf.load<T>(voff, i * sstride);
     });
-    T cv[N + 7];
-    line_cells<T, N, M, G>(v, cv, kc);
-    if (!partials) {
-        store_shifted<T, N>(cv, sigma, [&](int j, T x) { buf.store<T>(x, voff, j * sstride); });
-    } else {
-        double s = 0.0, s2 = 0.0, sj = 0.0;
-        store_shifted<T, N>(cv, sigma, [&](int j, T x) {
-            buf.store<T>(x, voff, j * sstride);
-            const double y = (double)x;
-            s += y;
-            s2 = fma(y, y, s2);
-            sj = fma((double)j, y, sj);
-        });
+    double s = 0.0, s2 = 0.0, sj = 0.0;
+    dispatch_sigma(sigma, [&](auto sc) {
+        constexpr int SIG = decltype(sc)::value;
+        if (!partials) {
+            advect_line<T, N, M, G, SIG>(v, kc, sigma, [&](int j, T x) { buf.store<T>(x, voff, j * sstride); });
+        } else {
+            advect_line<T, N, M, G, SIG>(v, kc, sigma, [&](int j, T x) {
+                buf.store<T>(x, voff, j * sstride);
+                const double y = (double)x;
+                s += y;
+                s2 = fma(y, y, s2);
+                sj = fma((double)j, y, sj);
+            });
+        }
+    });
+    if (partials) {
         double acc[5];
         acc[0] = s;
         acc[1] = s2;

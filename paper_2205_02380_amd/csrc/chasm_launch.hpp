@@ -21,13 +21,32 @@ struct Launch {
     static constexpr int reduce_nt = 256;
 };
 
+// Resident blocks of kernel k on the current device (CUs x blocks per CU), cached
+// per device and kernel.
+template <typename K>
+int resident_blocks(K k, int threads)
+{
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cache[dev] == 0) {
+        int ncu = 0, per = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, threads, 0) != hipSuccess) return 0;
+        cache[dev] = ncu * (per > 0 ? per : 1);
+    }
+    return cache[dev];
+}
+
 template <typename T, int N, int M, int G>
 hipError_t launch_cube(const JobDev& job, double* partials, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     if constexpr (Lc::cube_fits) {
-        hipLaunchKernelGGL((k_cube<T, N, M, G, Lc::cube_nt>), dim3((unsigned)job.nitems), dim3(Lc::cube_nt), 0, s, job,
-                           partials);
+        auto k = k_cube<T, N, M, G, Lc::cube_nt>;
+        const long long res = resident_blocks(k, Lc::cube_nt);
+        const unsigned grid = (unsigned)(res > 0 && res < job.nitems ? res : job.nitems);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(Lc::cube_nt), 0, s, job, partials);
         return hipGetLastError();
     } else {
         return hipErrorInvalidConfiguration;

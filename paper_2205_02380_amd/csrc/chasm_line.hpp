@@ -41,11 +41,13 @@ struct Shape {
     __host__ __device__ static constexpr int cells(int l) { return l == P - 1 ? MLAST : M; }
 };
 
-// Per-axis coefficients as seen by one line (uniform across a work-group).
-template <typename T>
+// Per-axis coefficients as seen by one line (uniform across a work-group).  Ptr is the
+// table pointer type: kernels read through the constant address space so the
+// compiler keeps the coefficients in SGPRs (scalar loads); host builds use const T*.
+template <typename T, typename Ptr = const T*>
 struct AxisCoef {
-    const T* __restrict__ stencil;   // [(P+1)][2G+1]
-    const T* __restrict__ fac;       // [2][3][MF]: inv, a*inv, c' for m = M (0), m = MLAST (1)
+    Ptr stencil;                     // [(P+1)][2G+1]
+    Ptr fac;                         // [2][3][MF]: inv, a*inv, c' for m = M (0), m = MLAST (1)
     T h3;                            // h/3
     T twoh;                          // 2h
     T w0, w1, w2, w3;                // shift weights of this line's k
@@ -68,9 +70,11 @@ constexpr int CV_OFF = 4;
 template <int N>
 struct CellCount { static constexpr int value = N + 7; };
 
-// Cell values of one line.  v[N] in, cv[c + CV_OFF] out for c in [-4, N+2].
-template <typename T, int N, int M, int G>
-__host__ __device__ __forceinline__ void line_cells(const T (&v)[N], T (&cv)[N + 7], const AxisCoef<T>& k)
+// Cell values of one line, handed out as soon as each patch is solved:
+// emit(std::integral_constant<int, c>{}, value) for c in [-4, N+2].  Emitting early
+// keeps only one patch's coefficients live at a time.
+template <typename T, int N, int M, int G, typename Ptr, typename Emit>
+__host__ __device__ __forceinline__ void line_emit(const T (&v)[N], const AxisCoef<T, Ptr>& k, Emit&& emit)
 {
     using S = Shape<N, M>;
     constexpr int P = S::P;
@@ -94,10 +98,10 @@ __host__ __device__ __forceinline__ void line_cells(const T (&v)[N], T (&cv)[N +
         constexpr int l = decltype(lc)::value;
         constexpr int s = S::start(l);
         constexpr int m = S::cells(l);
-        const T* __restrict__ f = k.fac + (l == P - 1 ? 3 * MF : 0);
-        const T* __restrict__ inv = f;
-        const T* __restrict__ ainv = f + MF;
-        const T* __restrict__ cp = f + 2 * MF;
+        const Ptr f = k.fac + (l == P - 1 ? 3 * MF : 0);
+        const Ptr inv = f;
+        const Ptr ainv = f + MF;
+        const Ptr cp = f + 2 * MF;
 
         // 2. forward sweep of the reduced tridiagonal system
         T e[m + 1];
@@ -125,41 +129,49 @@ __host__ __device__ __forceinline__ void line_cells(const T (&v)[N], T (&cv)[N +
             a = fma(k.w1, eta[nu + 1], a);
             a = fma(k.w2, eta[nu + 2], a);
             a = fma(k.w3, eta[nu + 3], a);
-            cv[s + nu + CV_OFF] = a;
+            emit(std::integral_constant<int, s + nu>{}, a);
         });
         if constexpr (l == 0) {
             // beyond the left end: eta_{-2} is the ghost, further out zero
             const T gl = k.ghost * (4 * eta[0] - 6 * eta[1] + 4 * eta[2] - eta[3]);
-            cv[3] = fma(k.w3, eta[2], fma(k.w2, eta[1], fma(k.w1, eta[0], k.w0 * gl)));   // c = -1
-            cv[2] = fma(k.w3, eta[1], fma(k.w2, eta[0], k.w1 * gl));                     // c = -2
-            cv[1] = fma(k.w3, eta[0], k.w2 * gl);                                         // c = -3
-            cv[0] = k.w3 * gl;                                                            // c = -4
+            emit(std::integral_constant<int, -1>{}, fma(k.w3, eta[2], fma(k.w2, eta[1], fma(k.w1, eta[0], k.w0 * gl))));
+            emit(std::integral_constant<int, -2>{}, fma(k.w3, eta[1], fma(k.w2, eta[0], k.w1 * gl)));
+            emit(std::integral_constant<int, -3>{}, fma(k.w3, eta[0], k.w2 * gl));
+            emit(std::integral_constant<int, -4>{}, k.w3 * gl);
         }
         if constexpr (l == P - 1) {
             // beyond the right end: eta_{m+2} is the ghost
             const T gr = k.ghost * (4 * eta[m + 2] - 6 * eta[m + 1] + 4 * eta[m] - eta[m - 1]);
-            cv[N + 3] = fma(k.w3, gr, fma(k.w2, eta[m + 2], fma(k.w1, eta[m + 1], k.w0 * eta[m])));  // c = N-1
-            cv[N + 4] = fma(k.w2, gr, fma(k.w1, eta[m + 2], k.w0 * eta[m + 1]));                    // c = N
-            cv[N + 5] = fma(k.w1, gr, k.w0 * eta[m + 2]);                                          // c = N+1
-            cv[N + 6] = k.w0 * gr;                                                                 // c = N+2
+            emit(std::integral_constant<int, N - 1>{},
+                 fma(k.w3, gr, fma(k.w2, eta[m + 2], fma(k.w1, eta[m + 1], k.w0 * eta[m]))));
+            emit(std::integral_constant<int, N>{}, fma(k.w2, gr, fma(k.w1, eta[m + 2], k.w0 * eta[m + 1])));
+            emit(std::integral_constant<int, N + 1>{}, fma(k.w1, gr, k.w0 * eta[m + 2]));
+            emit(std::integral_constant<int, N + 2>{}, k.w0 * gr);
         }
     });
 }
 
+// Cell values of one line.  v[N] in, cv[c + CV_OFF] out for c in [-4, N+2].
+template <typename T, int N, int M, int G, typename Ptr>
+__host__ __device__ __forceinline__ void line_cells(const T (&v)[N], T (&cv)[N + 7], const AxisCoef<T, Ptr>& k)
+{
+    line_emit<T, N, M, G>(v, k, [&](auto cc, T x) { cv[decltype(cc)::value + CV_OFF] = x; });
+}
+
 // Write output node j = c - sigma for every cell value; nodes whose departure cell
 // lies further out than the ghost cells get 0.  st(j, value) performs the store with
-// a compile-time j.  sigma is uniform over the work-group: the common cases
-// sigma in {0, -1} (|alpha| < 1) store straight from the cell values; any other
-// shift moves the cell values through a register barrel shifter (one stage per bit of
-// |sigma + CV_OFF|, each a compile-time shift selected by that bit).
-template <typename T, int N, typename Store>
-__host__ __device__ __forceinline__ void store_shifted(const T (&cv)[N + 7], int sigma, Store st)
+// a compile-time j.  sigma is uniform over a work-group for a whole sweep, so callers
+// dispatch once per sweep on SIG: 0 and -1 (|alpha| < 1) store straight from the cell
+// values; SIG_ANY handles any other shift through a register barrel shifter (one
+// stage per bit of |sigma + CV_OFF|, each a compile-time shift selected by that bit).
+constexpr int SIG_ANY = 1;
+
+template <typename T, int N, int SIG, typename Store>
+__host__ __device__ __forceinline__ void store_cells(const T (&cv)[N + 7], int sigma, Store st)
 {
     constexpr int K = N + 7;
-    if (sigma == 0) {
-        static_for<0, N>([&](auto jc) { st(decltype(jc)::value, cv[decltype(jc)::value + CV_OFF]); });
-    } else if (sigma == -1) {
-        static_for<0, N>([&](auto jc) { st(decltype(jc)::value, cv[decltype(jc)::value + CV_OFF - 1]); });
+    if constexpr (SIG == 0 || SIG == -1) {
+        static_for<0, N>([&](auto jc) { st(decltype(jc)::value, cv[decltype(jc)::value + CV_OFF + SIG]); });
     } else {
         // out[j] = cv[j + u] with u = sigma + CV_OFF (zero outside 0..K-1)
         const int u = sigma + CV_OFF;
@@ -189,6 +201,40 @@ __host__ __device__ __forceinline__ void store_shifted(const T (&cv)[N + 7], int
         }
         static_for<0, N>([&](auto jc) { st(decltype(jc)::value, a[decltype(jc)::value]); });
     }
+}
+
+// Run body(std::integral_constant<int, SIG>) with SIG matching sigma's class.
+template <typename Body>
+__host__ __device__ __forceinline__ void dispatch_sigma(int sigma, Body&& body)
+{
+    if (sigma == 0) body(std::integral_constant<int, 0>{});
+    else if (sigma == -1) body(std::integral_constant<int, -1>{});
+    else body(std::integral_constant<int, SIG_ANY>{});
+}
+
+// One line, computed and stored: for SIG 0 / -1 each cell value goes straight to its
+// output node j = c - SIG as soon as its patch is solved; SIG_ANY collects the cell
+// values and moves them through the barrel shifter.
+template <typename T, int N, int M, int G, int SIG, typename Ptr, typename Store>
+__host__ __device__ __forceinline__ void advect_line(const T (&v)[N], const AxisCoef<T, Ptr>& k, int sigma, Store st)
+{
+    if constexpr (SIG == 0 || SIG == -1) {
+        line_emit<T, N, M, G>(v, k, [&](auto cc, T x) {
+            constexpr int j = decltype(cc)::value - SIG;
+            if constexpr (j >= 0 && j < N) st(j, x);
+        });
+    } else {
+        T cv[N + 7];
+        line_cells<T, N, M, G>(v, cv, k);
+        store_cells<T, N, SIG_ANY>(cv, sigma, st);
+    }
+}
+
+// Convenience form with the dispatch inside (one line; used off the hot loops).
+template <typename T, int N, typename Store>
+__host__ __device__ __forceinline__ void store_shifted(const T (&cv)[N + 7], int sigma, Store st)
+{
+    dispatch_sigma(sigma, [&](auto sc) { store_cells<T, N, decltype(sc)::value>(cv, sigma, st); });
 }
 
 }  // namespace chasm

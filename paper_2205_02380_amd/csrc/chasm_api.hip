@@ -21,7 +21,7 @@ namespace chasm {
 
 // ---------------------------------------------------------------------------
 // Kernel registry: every compiled (dtype, N, M, G).
-#define CHASM_DECL(T, N, M, G) extern template const KernelSet* kernel_set<T, N, M, G>();
+#define CHASM_DECL(T, N, M, G, CL) extern template const KernelSet* kernel_set<T, N, M, G, CL>();
 CHASM_SHAPES(CHASM_DECL)
 #undef CHASM_DECL
 
@@ -29,7 +29,7 @@ static const std::vector<const KernelSet*>& registry()
 {
     static const std::vector<const KernelSet*> all = [] {
         std::vector<const KernelSet*> v;
-#define CHASM_REG(T, N, M, G) v.push_back(kernel_set<T, N, M, G>());
+#define CHASM_REG(T, N, M, G, CL) v.push_back(kernel_set<T, N, M, G, CL>());
         CHASM_SHAPES(CHASM_REG)
 #undef CHASM_REG
         return v;
@@ -37,15 +37,12 @@ static const std::vector<const KernelSet*>& registry()
     return all;
 }
 
-// Smallest compiled window G >= g for (dtype, N, M).
-static const KernelSet* find_kernels(int dtype, int N, int M, int g)
+// The compiled kernels of (dtype, N, M, g, closure), or nullptr.
+static const KernelSet* find_kernels(int dtype, int N, int M, int g, int closure)
 {
-    const KernelSet* best = nullptr;
-    for (const KernelSet* k : registry()) {
-        if (k->dtype != dtype || k->N != N || k->M != M || k->G < g) continue;
-        if (!best || k->G < best->G) best = k;
-    }
-    return best;
+    for (const KernelSet* k : registry())
+        if (k->dtype == dtype && k->N == N && k->M == M && k->G == g && k->CL == closure) return k;
+    return nullptr;
 }
 
 // ---------------------------------------------------------------------------
@@ -157,11 +154,11 @@ static chasm_status validate(const chasm_advect_desc* d, const KernelSet** ks_ou
         return fail(CHASM_EUNSUPPORTED, "kernels are built for equal nx on the three axes");
     if (d->patch[0] != d->patch[1] || d->patch[0] != d->patch[2])
         return fail(CHASM_EUNSUPPORTED, "kernels are built for equal patch sizes on the three axes");
-    const KernelSet* ks = find_kernels(d->dtype, d->nx[0], d->patch[0], d->ghost);
+    const KernelSet* ks = find_kernels(d->dtype, d->nx[0], d->patch[0], d->ghost, d->closure);
     if (!ks) {
         char buf[160];
-        std::snprintf(buf, sizeof buf, "no kernel built for dtype=%d nx=%d patch=%d ghost=%d", d->dtype, d->nx[0],
-                      d->patch[0], d->ghost);
+        std::snprintf(buf, sizeof buf, "no kernel built for dtype=%d nx=%d patch=%d ghost=%d closure=%d", d->dtype,
+                      d->nx[0], d->patch[0], d->ghost, d->closure);
         return fail(CHASM_EUNSUPPORTED, buf);
     }
     if (d->schedule == CHASM_SCHED_CUBE && !ks->cube)
@@ -185,11 +182,12 @@ static long long step_partial_rows(const chasm_advect_desc* d, const KernelSet* 
     return nkp * (sched == CHASM_SCHED_CUBE ? ks->cube_rows : ks->pencil_rows);
 }
 
+// Device table block: per axis the FP64 shift weights, their FP32 mirror and the
+// integer shift classes.  (Stencil rows and patch factors are compile-time constants
+// of the kernels; the host builds the stencil rows too, for the record and the tests.)
 struct TableBlock {
     std::vector<char> bytes;
-    size_t off_f64[3][4];   // stencil, fac, w, (unused) per axis, FP64
-    size_t off_f32[3][4];
-    size_t off_shift[3];
+    size_t off_w64[3], off_w32[3], off_shift[3];
 };
 
 template <typename V>
@@ -212,15 +210,9 @@ static bool build_tables(const chasm_advect_desc* d, const KernelSet* ks, TableB
             return false;
     }
     for (int a = 0; a < 3; ++a) {
-        tb.off_f64[a][0] = push(tb.bytes, at[a].stencil.data(), at[a].stencil.size());
-        tb.off_f64[a][1] = push(tb.bytes, at[a].fac.data(), at[a].fac.size());
-        tb.off_f64[a][2] = push(tb.bytes, at[a].w.data(), at[a].w.size());
-        std::vector<float> s32(at[a].stencil.begin(), at[a].stencil.end());
-        std::vector<float> f32(at[a].fac.begin(), at[a].fac.end());
+        tb.off_w64[a] = push(tb.bytes, at[a].w.data(), at[a].w.size());
         std::vector<float> w32(at[a].w.begin(), at[a].w.end());
-        tb.off_f32[a][0] = push(tb.bytes, s32.data(), s32.size());
-        tb.off_f32[a][1] = push(tb.bytes, f32.data(), f32.size());
-        tb.off_f32[a][2] = push(tb.bytes, w32.data(), w32.size());
+        tb.off_w32[a] = push(tb.bytes, w32.data(), w32.size());
         tb.off_shift[a] = push(tb.bytes, at[a].shift.data(), at[a].shift.size());
     }
     return true;
@@ -345,20 +337,14 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
     h->job.nitems = nkp * desc->nbatch;
     for (int a = 0; a < 3; ++a) {
         h->job.nk[a] = desc->nk[a];
-        const size_t* off = f64 ? tb.off_f64[a] : tb.off_f32[a];
-        h->job.ax[a].stencil = tbase + off[0];
-        h->job.ax[a].fac = tbase + off[1];
-        h->job.ax[a].w = tbase + off[2];
+        h->job.ax[a].w = tbase + (f64 ? tb.off_w64[a] : tb.off_w32[a]);
         h->job.ax[a].shift = reinterpret_cast<const int*>(tbase + tb.off_shift[a]);
         const double hx = (desc->x_hi[a] - desc->x_lo[a]) / desc->nx[a];
-        h->job.ax[a].h3 = hx / 3.0;
-        h->job.ax[a].twoh = 2.0 * hx;
         h->fin.xlo[a] = desc->x_lo[a];
         h->fin.hx[a] = hx;
         h->fin.klo[a] = desc->k_lo[a];
         h->fin.hk[a] = (desc->k_hi[a] - desc->k_lo[a]) / desc->nk[a];
     }
-    h->job.ghost = desc->closure == CHASM_CLOSURE_POLY3 ? 1.0 : 0.0;
     h->fin.vol = h->fin.hx[0] * h->fin.hx[1] * h->fin.hx[2] * h->fin.hk[0] * h->fin.hk[1] * h->fin.hk[2];
 
     if (desc->flags & CHASM_FLAG_GRAPH) {

@@ -27,18 +27,14 @@
 namespace chasm {
 
 struct AxisTabDev {
-    const void* stencil;   // T[(P+1)][2G+1]
-    const void* fac;       // T[2][3][M+1]
     const int* shift;      // int[nk]   sigma = floor(-alpha(k))
     const void* w;         // T[nk][4]  shift weights
-    double h3, twoh;
 };
 
 struct JobDev {
     void* f;               // field base (caller-owned device memory)
     long long nitems;      // nbatch * nk1 * nk2 * nk3
     int nk[3];
-    double ghost;          // 0 paper closure, 1 cubic-exact closure
     AxisTabDev ax[3];
 };
 
@@ -118,13 +114,15 @@ struct Buf {
     }
 };
 
+// k indices of an item (items < 2^31 and k-points per field < 2^31: validated on the host).
 __device__ __forceinline__ void item_k(const JobDev& job, long long item, int ik[3])
 {
-    const long long nkp = (long long)job.nk[0] * job.nk[1] * job.nk[2];
-    const int kf = (int)(item % nkp);
-    ik[0] = kf % job.nk[0];
-    ik[1] = (kf / job.nk[0]) % job.nk[1];
-    ik[2] = kf / (job.nk[0] * job.nk[1]);
+    const unsigned nk0 = (unsigned)job.nk[0], nk1 = (unsigned)job.nk[1];
+    const unsigned nkp = nk0 * nk1 * (unsigned)job.nk[2];
+    const unsigned kf = (unsigned)item % nkp;
+    ik[0] = (int)(kf % nk0);
+    ik[1] = (int)((kf / nk0) % nk1);
+    ik[2] = (int)(kf / (nk0 * nk1));
 }
 
 // Tables are read-only for the whole kernel: read them through the constant address
@@ -133,20 +131,15 @@ template <typename T>
 using cptr = const T __attribute__((address_space(4)))*;
 
 template <typename T>
-__device__ __forceinline__ AxisCoef<T, cptr<T>> axis_coef(const JobDev& job, int d, int ik, int& sigma)
+__device__ __forceinline__ AxisCoef<T> axis_coef(const JobDev& job, int d, int ik, int& sigma)
 {
     const AxisTabDev& a = job.ax[d];
-    AxisCoef<T, cptr<T>> c;
-    c.stencil = (cptr<T>)(a.stencil);
-    c.fac = (cptr<T>)(a.fac);
-    c.h3 = (T)a.h3;
-    c.twoh = (T)a.twoh;
     const cptr<T> w = (cptr<T>)(a.w) + 4 * ik;
+    AxisCoef<T> c;
     c.w0 = w[0];
     c.w1 = w[1];
     c.w2 = w[2];
     c.w3 = w[3];
-    c.ghost = (T)job.ghost;
     sigma = ((const int __attribute__((address_space(4)))*)(a.shift))[ik];
     return c;
 }
@@ -207,7 +200,7 @@ __device__ __forceinline__ void write_partials(double (&acc)[5], const int ik[3]
 // round -- or, after the last round, the next item's first round -- is already in
 // flight into VGPRs (N/VW 16-byte buffer loads per lane).  The x3 sweep then runs on
 // the whole cube and the result streams out, with the FP64 partials when asked for.
-template <typename T, int N, int M, int G, int NT>
+template <typename T, int N, int M, int G, int CL, int NT, bool RED>
 __global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ partials)
 {
     constexpr int PX = N + 1;
@@ -216,128 +209,151 @@ __global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ pa
     constexpr int ROUNDS = N / PL;
     constexpr int RV = N / VW;                    // 16-byte vectors per lane per round
     constexpr int NV = N * N * N / VW;            // 16-byte vectors per cube
+    constexpr int RSTEP = NT * VW / N;            // cube rows between a lane's vectors
     constexpr uint32_t CUBE_BYTES = (uint32_t)(N * N * N * sizeof(T));
-    static_assert(NT % N == 0 && N % PL == 0 && N % VW == 0 && NV % NT == 0, "bad cube tiling");
+    static_assert(NT % N == 0 && N % PL == 0 && N % VW == 0 && NV % NT == 0 && (NT * VW) % N == 0,
+                  "bad cube tiling");
     using V = typename Vec16<T>::type;
     __shared__ T lds[N * N * PX];
 
-    // tid is re-derived inside the item loop through an opaque copy, so per-lane
-    // addresses and coordinates are recomputed per item instead of being hoisted out
-    // of the loop and pinned in registers for its whole length.
-    int tid = (int)threadIdx.x;
+    // Per-lane bases; every other index below is a compile-time offset from them.
+    // tid is re-derived inside the item loop through an opaque copy, so the bases are
+    // recomputed per item instead of being pinned in registers for the whole loop.
+    unsigned tid = threadIdx.x;
     V pre[RV];
     auto fetch = [&](long long it, int round) {
-        const uint32_t voff = (uint32_t)tid * 16u;
         const Buf b(static_cast<const T*>(job.f) + it * (long long)(N * N * N), CUBE_BYTES);
         static_for<0, RV>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            pre[q] = b.template load16<T>(voff, (uint32_t)((round * RV + q) * NT * 16));
+            pre[q] = b.template load16<T>(tid * 16u, (uint32_t)((round * RV + q) * NT * 16));
         });
     };
-    auto fill = [&](int round) {
+
+    // Round r of an item: LDS rows of planes [r*PL, (r+1)*PL) from pre[].
+    auto fill = [&](int r) {
+        const unsigned vbase = (tid * VW / N) * PX + (tid * VW) % N;
         static_for<0, RV>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            const int e = (round * RV + q) * NT + tid;                     // vector index in the cube
-            const int row = (e * VW) / N, x1 = (e * VW) % N;
+            T* dst = lds + vbase + (unsigned)((r * RV + q) * RSTEP * PX);
 #pragma unroll
-            for (int i = 0; i < VW; ++i) lds[row * PX + x1 + i] = vget<T>(pre[q], i);
+            for (int i = 0; i < VW; ++i) dst[i] = vget<T>(pre[q], i);
         });
     };
 
     long long item = blockIdx.x;
-    if (item < job.nitems) fetch(item, 0);
-    for (; item < job.nitems; item += gridDim.x) {
-        tid = (int)threadIdx.x;
+    if (item >= job.nitems) return;
+    fetch(item, 0);
+    fill(0);
+    // The loop is rotated: an item's first round is written to LDS at the end of the
+    // previous iteration.
+    for (;;) {
+        tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
+        // vector v = q*NT + tid of the cube holds elements (q*NT + tid)*VW.. : its row is
+        // q*RSTEP + tid*VW/N and its first x1 is tid*VW % N
+        const unsigned vbase = (tid * VW / N) * PX + (tid * VW) % N;
+        const unsigned plane_t = tid / N, lane_t = tid % N;
+        const long long next = item + gridDim.x;
         int ik[3];
         item_k(job, item, ik);
         int sig0, sig1;
         const auto k0 = axis_coef<T>(job, 0, ik[0], sig0);
         const auto k1 = axis_coef<T>(job, 1, ik[1], sig1);
-        const int plane_t = tid / N, lane_t = tid % N;
 
 #pragma unroll 1
         for (int r = 0; r < ROUNDS; ++r) {
-            fill(r);
+            if (r > 0) fill(r);
             __syncthreads();
             if (r + 1 < ROUNDS) fetch(item, r + 1);
-            else if (item + gridDim.x < job.nitems) fetch(item + gridDim.x, 0);
-            const int plane = r * PL + plane_t;
+            else if (next < job.nitems) fetch(next, 0);
+            const unsigned plane = r * PL + plane_t;
             {   // x1: row (x2 = lane_t) of this thread's plane
-                const int base = (plane * N + lane_t) * PX;
+                T* row = lds + (plane * N + lane_t) * PX;
                 dispatch_sigma(sig0, [&](auto sc) {
                     T v[N];
 #pragma unroll
-                    for (int i = 0; i < N; ++i) v[i] = lds[base + i];
-                    advect_line<T, N, M, G, decltype(sc)::value>(v, k0, sig0, [&](int j, T x) { lds[base + j] = x; });
+                    for (int i = 0; i < N; ++i) v[i] = row[i];
+                    advect_line<T, N, M, G, CL, decltype(sc)::value>(v, k0, sig0, [&](int j, T x) { row[j] = x; });
                 });
             }
             __syncthreads();
             {   // x2: column (x1 = lane_t) of this thread's plane
-                const int base = plane * N * PX + lane_t;
+                T* col = lds + plane * N * PX + lane_t;
                 dispatch_sigma(sig1, [&](auto sc) {
                     T v[N];
 #pragma unroll
-                    for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
-                    advect_line<T, N, M, G, decltype(sc)::value>(v, k1, sig1,
-                                                                   [&](int j, T x) { lds[base + j * PX] = x; });
+                    for (int i = 0; i < N; ++i) v[i] = col[i * PX];
+                    advect_line<T, N, M, G, CL, decltype(sc)::value>(v, k1, sig1,
+                                                                       [&](int j, T x) { col[j * PX] = x; });
                 });
             }
         }
         __syncthreads();
-        {   // x3 over the whole cube
+        {   // x3 over the whole cube: lines (x1, x2) = (l % N, l / N), l = tid + q*NT
             int sig2;
             const auto k2 = axis_coef<T>(job, 2, ik[2], sig2);
+            const unsigned lbase = plane_t * PX + lane_t;
             dispatch_sigma(sig2, [&](auto sc) {
                 constexpr int SIG = decltype(sc)::value;
-#pragma unroll 1
-                for (int l = tid; l < N * N; l += NT) {
-                    const int base = (l / N) * PX + (l % N);                // (x1, x2)
+                static_for<0, N * N / NT>([&](auto qc) {
+                    T* line = lds + lbase + (unsigned)(decltype(qc)::value * PL * PX);
                     T v[N];
 #pragma unroll
-                    for (int i = 0; i < N; ++i) v[i] = lds[base + i * N * PX];
-                    advect_line<T, N, M, G, SIG>(v, k2, sig2, [&](int j, T x) { lds[base + j * N * PX] = x; });
-                }
+                    for (int i = 0; i < N; ++i) v[i] = line[i * N * PX];
+                    advect_line<T, N, M, G, CL, SIG>(v, k2, sig2, [&](int j, T x) { line[j * N * PX] = x; });
+                });
             });
         }
         __syncthreads();
 
-        const Buf b(static_cast<T*>(job.f) + item * (long long)(N * N * N), CUBE_BYTES);
-        const uint32_t voff = (uint32_t)tid * 16u;
+        // Read the finished cube out of LDS; it is stored only after the next item's
+        // first round has been written to LDS (below), so no store is ever issued
+        // between a prefetch load and the point where its data is consumed.
+        V out[NV / NT];
         double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        const unsigned row_t = tid * VW / N, x1_t = (tid * VW) % N;
         static_for<0, NV / NT>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            const int e = q * NT + tid;
-            const int row = (e * VW) / N, x1 = (e * VW) % N;
-            V x;
+            const T* src = lds + vbase + (unsigned)(q * RSTEP * PX);
             double sum = 0.0;
 #pragma unroll
             for (int i = 0; i < VW; ++i) {
-                const T y = lds[row * PX + x1 + i];
-                vset<T>(x, i, y);
-                if (partials) {
+                const T y = src[i];
+                vset<T>(out[q], i, y);
+                if constexpr (RED) {
                     const double yd = (double)y;
                     sum += yd;
                     acc[1] = fma(yd, yd, acc[1]);
-                    acc[2] = fma((double)(x1 + i), yd, acc[2]);
+                    acc[2] = fma((double)i, yd, acc[2]);
                 }
             }
-            b.template store16<T>(x, voff, (uint32_t)(q * NT * 16));
-            if (partials) {
+            if constexpr (RED) {
+                const unsigned row = q * RSTEP + row_t;
                 acc[0] += sum;
                 acc[3] = fma((double)(row % N), sum, acc[3]);
                 acc[4] = fma((double)(row / N), sum, acc[4]);
             }
         });
-        if (partials) write_partials<NT>(acc, ik, partials + item * NRED);
+        if constexpr (RED) {
+            acc[2] = fma((double)x1_t, acc[0], acc[2]);   // sum (x1_t + i) f
+            write_partials<NT>(acc, ik, partials + item * NRED);
+        }
         __syncthreads();
+        if (next < job.nitems) fill(0);
+        const Buf b(static_cast<T*>(job.f) + item * (long long)(N * N * N), CUBE_BYTES);
+        static_for<0, NV / NT>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            b.template store16<T>(out[q], tid * 16u, (uint32_t)(q * NT * 16));
+        });
+        if (next >= job.nitems) break;
+        item = next;
     }
 }
 
 // ---------------------------------------------------------------------------
 // S x3-slabs (N x N each) per block in LDS: x1 sweep, then (X2 = true) the x2 sweep
 // stored straight to global memory.  Block = S*N threads, one line each.
-template <typename T, int N, int M, int G, int S, bool X2>
+template <typename T, int N, int M, int G, int CL, int S, bool X2>
 __global__ __launch_bounds__(S * N) void k_slab(JobDev job)
 {
     constexpr int PX = N + 1;
@@ -372,7 +388,7 @@ __global__ __launch_bounds__(S * N) void k_slab(JobDev job)
             T v[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) v[i] = lds[base + i];
-            advect_line<T, N, M, G, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { lds[base + j] = x; });
+            advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { lds[base + j] = x; });
         });
     }
     __syncthreads();
@@ -397,7 +413,7 @@ __global__ __launch_bounds__(S * N) void k_slab(JobDev job)
             T v[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
-            advect_line<T, N, M, G, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { out[j * N] = x; });
+            advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { out[j * N] = x; });
         });
     }
 }
@@ -405,7 +421,7 @@ __global__ __launch_bounds__(S * N) void k_slab(JobDev job)
 // ---------------------------------------------------------------------------
 // One line per lane along axis AXIS (1: x2, 2: x3), NT lines per block; NT divides
 // N*N so a block never straddles two items.  Optional fused FP64 partials.
-template <typename T, int N, int M, int G, int NT, int AXIS>
+template <typename T, int N, int M, int G, int CL, int NT, int AXIS, bool RED>
 __global__ __launch_bounds__(NT) void k_pencil(JobDev job, double* __restrict__ partials)
 {
     static_assert((N * N) % NT == 0, "block must tile the lines of one item");
@@ -433,10 +449,10 @@ __global__ __launch_bounds__(NT) void k_pencil(JobDev job, double* __restrict__ 
     double s = 0.0, s2 = 0.0, sj = 0.0;
     dispatch_sigma(sigma, [&](auto sc) {
         constexpr int SIG = decltype(sc)::value;
-        if (!partials) {
-            advect_line<T, N, M, G, SIG>(v, kc, sigma, [&](int j, T x) { buf.store<T>(x, voff, j * sstride); });
+        if constexpr (!RED) {
+            advect_line<T, N, M, G, CL, SIG>(v, kc, sigma, [&](int j, T x) { buf.store<T>(x, voff, j * sstride); });
         } else {
-            advect_line<T, N, M, G, SIG>(v, kc, sigma, [&](int j, T x) {
+            advect_line<T, N, M, G, CL, SIG>(v, kc, sigma, [&](int j, T x) {
                 buf.store<T>(x, voff, j * sstride);
                 const double y = (double)x;
                 s += y;
@@ -445,7 +461,7 @@ __global__ __launch_bounds__(NT) void k_pencil(JobDev job, double* __restrict__ 
             });
         }
     });
-    if (partials) {
+    if constexpr (RED) {
         double acc[5];
         acc[0] = s;
         acc[1] = s2;

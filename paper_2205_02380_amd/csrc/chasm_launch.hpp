@@ -13,7 +13,10 @@ template <typename T, int N>
 struct Launch {
     // Whole x-cube in LDS (rows padded to N+1) plus the block-sum scratch.
     static constexpr bool cube_fits = (size_t)N * N * (N + 1) * sizeof(T) + 1024 <= kLdsBytes;
-    static constexpr int cube_nt = N <= 8 ? 64 : (N <= 16 ? 256 : (N <= 24 ? 192 : 512));
+    // threads per cube block: a multiple of N whose planes-per-round NT/N divide N;
+    // FP32 uses one line per thread per sweep up to N = 32 (4 waves per SIMD)
+    static constexpr int cube_nt =
+        N <= 8 ? 64 : (N <= 16 ? 256 : (N <= 24 ? (sizeof(T) == 4 ? 576 : 192) : 1024));
     // x3-slabs per slab block: S*N threads, a multiple of 64, S | N.
     static constexpr int slab_s = N == 8 ? 8 : (N == 16 ? 4 : (N == 24 ? 8 : (N == 32 ? 2 : (N == 48 ? 4 : 1))));
     // lines per pencil block: a multiple of 64 dividing N*N.
@@ -38,38 +41,44 @@ int resident_blocks(K k, int threads)
     return cache[dev];
 }
 
-template <typename T, int N, int M, int G>
+template <typename T, int N, int M, int G, int CL>
 hipError_t launch_cube(const JobDev& job, double* partials, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     if constexpr (Lc::cube_fits) {
-        auto k = k_cube<T, N, M, G, Lc::cube_nt>;
-        const long long res = resident_blocks(k, Lc::cube_nt);
-        const unsigned grid = (unsigned)(res > 0 && res < job.nitems ? res : job.nitems);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(Lc::cube_nt), 0, s, job, partials);
-        return hipGetLastError();
+        auto launch = [&](auto k) {
+            const long long res = resident_blocks(k, Lc::cube_nt);
+            const unsigned grid = (unsigned)(res > 0 && res < job.nitems ? res : job.nitems);
+            hipLaunchKernelGGL(k, dim3(grid), dim3(Lc::cube_nt), 0, s, job, partials);
+            return hipGetLastError();
+        };
+        return partials ? launch(k_cube<T, N, M, G, CL, Lc::cube_nt, true>)
+                        : launch(k_cube<T, N, M, G, CL, Lc::cube_nt, false>);
     } else {
         return hipErrorInvalidConfiguration;
     }
 }
 
-template <typename T, int N, int M, int G, bool X2>
+template <typename T, int N, int M, int G, int CL, bool X2>
 hipError_t launch_slab(const JobDev& job, double*, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     constexpr int S = Lc::slab_s;
     const unsigned grid = (unsigned)(job.nitems * (N / S));
-    hipLaunchKernelGGL((k_slab<T, N, M, G, S, X2>), dim3(grid), dim3(S * N), 0, s, job);
+    hipLaunchKernelGGL((k_slab<T, N, M, G, CL, S, X2>), dim3(grid), dim3(S * N), 0, s, job);
     return hipGetLastError();
 }
 
-template <typename T, int N, int M, int G, int AXIS>
+template <typename T, int N, int M, int G, int CL, int AXIS>
 hipError_t launch_pencil(const JobDev& job, double* partials, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     constexpr int NT = Lc::pencil_nt;
     const unsigned grid = (unsigned)(job.nitems * (N * N / NT));
-    hipLaunchKernelGGL((k_pencil<T, N, M, G, NT, AXIS>), dim3(grid), dim3(NT), 0, s, job, partials);
+    if (partials)
+        hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, AXIS, true>), dim3(grid), dim3(NT), 0, s, job, partials);
+    else
+        hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, AXIS, false>), dim3(grid), dim3(NT), 0, s, job, partials);
     return hipGetLastError();
 }
 
@@ -82,7 +91,7 @@ hipError_t launch_reduce(const JobDev& job, double* partials, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int N, int M, int G>
+template <typename T, int N, int M, int G, int CL>
 const KernelSet* kernel_set()
 {
     using Lc = Launch<T, N>;
@@ -91,11 +100,12 @@ const KernelSet* kernel_set()
         N,
         M,
         G,
-        Lc::cube_fits ? &launch_cube<T, N, M, G> : nullptr,
-        &launch_slab<T, N, M, G, false>,
-        &launch_slab<T, N, M, G, true>,
-        &launch_pencil<T, N, M, G, 1>,
-        &launch_pencil<T, N, M, G, 2>,
+        CL,
+        Lc::cube_fits ? &launch_cube<T, N, M, G, CL> : nullptr,
+        &launch_slab<T, N, M, G, CL, false>,
+        &launch_slab<T, N, M, G, CL, true>,
+        &launch_pencil<T, N, M, G, CL, 1>,
+        &launch_pencil<T, N, M, G, CL, 2>,
         &launch_reduce<T, N>,
         1,
         N * N / Lc::pencil_nt,
@@ -103,6 +113,6 @@ const KernelSet* kernel_set()
     return &ks;
 }
 
-#define CHASM_INSTANTIATE(T, N, M, G) template const KernelSet* kernel_set<T, N, M, G>();
+#define CHASM_INSTANTIATE(T, N, M, G, CL) template const KernelSet* kernel_set<T, N, M, G, CL>();
 
 }  // namespace chasm

@@ -1,8 +1,9 @@
 // chasm_registry.hpp -- the compiled kernel shapes and their launchers.
 //
-// Every (T, N, M, G) below is compiled: element type T, N nodes per axis (equal on
-// all three axes), M cells per patch, G the largest ghost width the kernel's stencil
-// window holds (a handle with ghost g uses the smallest G >= g built for its N, M).
+// Every (T, N, M, G, CL) below is compiled: element type T, N nodes per axis (equal
+// on all three axes), M cells per patch, ghost width G, closure CL (0 the paper's
+// PMBC, 1 the cubic-exact variant).  The stencil rows and patch factors of a shape
+// are compile-time constants, so a handle needs an exact match.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -16,7 +17,7 @@ using LaunchFn = hipError_t (*)(const JobDev& job, double* partials, hipStream_t
 
 struct KernelSet {
     int dtype;              // 0 float, 1 double
-    int N, M, G;
+    int N, M, G, CL;
     LaunchFn cube;          // nullptr when the x-cube does not fit in LDS
     LaunchFn slab_x1;
     LaunchFn slab_x1x2;
@@ -27,21 +28,34 @@ struct KernelSet {
     int pencil_rows;        // partial rows per item written by pencil_x3
 };
 
-template <typename T, int N, int M, int G>
+template <typename T, int N, int M, int G, int CL>
 const KernelSet* kernel_set();
 
-// (T, N, M, G) shapes, grouped by (N, dtype): one compilation unit per group.
-// FP64 is built for the grids the plain FP64 form and the FP64 parity cases use.
-#define CHASM_SHAPES_N8_F32(X) X(float, 8, 2, 7) X(float, 8, 4, 7) X(float, 8, 8, 7)
-#define CHASM_SHAPES_N8_F64(X) X(double, 8, 2, 7) X(double, 8, 4, 7) X(double, 8, 8, 7)
-#define CHASM_SHAPES_N16_F32(X) X(float, 16, 4, 8) X(float, 16, 8, 8) X(float, 16, 16, 8) X(float, 16, 8, 15)
-#define CHASM_SHAPES_N16_F64(X) X(double, 16, 4, 8) X(double, 16, 8, 8) X(double, 16, 16, 8) X(double, 16, 8, 15)
-#define CHASM_SHAPES_N24_F32(X) X(float, 24, 8, 8) X(float, 24, 12, 8)
-#define CHASM_SHAPES_N24_F64(X) X(double, 24, 8, 8) X(double, 24, 12, 8)
-#define CHASM_SHAPES_N32_F32(X) X(float, 32, 8, 8) X(float, 32, 16, 8)
-#define CHASM_SHAPES_N32_F64(X) X(double, 32, 8, 8) X(double, 32, 16, 8)
-#define CHASM_SHAPES_N48_F32(X) X(float, 48, 8, 8) X(float, 48, 12, 8) X(float, 48, 16, 8)
-#define CHASM_SHAPES_N64_F32(X) X(float, 64, 8, 8) X(float, 64, 16, 8)
+// (T, N, M, G, CL) shapes, grouped by (N, dtype): one compilation unit per group.
+// FP32: the benchmark and serving grids, the autotuner's patch x ghost sweep for the
+// 32^3 / 48^3 / 64^3 grids, and the test shapes.  FP64: the plain FP64 form and the
+// FP64 parity cases.
+#define CHASM_SHAPES_N8_F32(X) X(float, 8, 2, 1, 0) X(float, 8, 4, 3, 0) X(float, 8, 8, 7, 0)
+#define CHASM_SHAPES_N8_F64(X) X(double, 8, 2, 1, 0) X(double, 8, 4, 3, 0) X(double, 8, 8, 7, 0)
+#define CHASM_SHAPES_N16_F32(X)                                                                        \
+    X(float, 16, 8, 4, 0) X(float, 16, 8, 4, 1) X(float, 16, 8, 6, 0) X(float, 16, 4, 8, 0)              \
+    X(float, 16, 8, 15, 0) X(float, 16, 16, 5, 0)
+#define CHASM_SHAPES_N16_F64(X)                                                                        \
+    X(double, 16, 8, 4, 0) X(double, 16, 8, 4, 1) X(double, 16, 8, 6, 0) X(double, 16, 4, 8, 0)          \
+    X(double, 16, 8, 15, 0) X(double, 16, 16, 5, 0)
+#define CHASM_SHAPES_N24_F32(X) X(float, 24, 8, 6, 0) X(float, 24, 12, 6, 0)
+#define CHASM_SHAPES_N24_F64(X) X(double, 24, 8, 6, 0) X(double, 24, 12, 6, 0)
+#define CHASM_SHAPES_N32_F32(X)                                                                        \
+    X(float, 32, 8, 4, 0) X(float, 32, 8, 6, 0) X(float, 32, 8, 8, 0) X(float, 32, 16, 4, 0)             \
+    X(float, 32, 16, 6, 0) X(float, 32, 16, 8, 0)
+#define CHASM_SHAPES_N32_F64(X) X(double, 32, 8, 6, 0) X(double, 32, 16, 8, 0)
+#define CHASM_SHAPES_N48_F32(X)                                                                        \
+    X(float, 48, 8, 4, 0) X(float, 48, 8, 6, 0) X(float, 48, 8, 8, 0) X(float, 48, 12, 4, 0)             \
+    X(float, 48, 12, 6, 0) X(float, 48, 12, 8, 0) X(float, 48, 16, 4, 0) X(float, 48, 16, 6, 0)          \
+    X(float, 48, 16, 8, 0)
+#define CHASM_SHAPES_N64_F32(X)                                                                        \
+    X(float, 64, 8, 4, 0) X(float, 64, 8, 6, 0) X(float, 64, 8, 8, 0) X(float, 64, 16, 4, 0)             \
+    X(float, 64, 16, 6, 0) X(float, 64, 16, 8, 0)
 #define CHASM_SHAPES(X)                                                                                   \
     CHASM_SHAPES_N8_F32(X) CHASM_SHAPES_N8_F64(X) CHASM_SHAPES_N16_F32(X) CHASM_SHAPES_N16_F64(X)          \
     CHASM_SHAPES_N24_F32(X) CHASM_SHAPES_N24_F64(X) CHASM_SHAPES_N32_F32(X) CHASM_SHAPES_N32_F64(X)        \

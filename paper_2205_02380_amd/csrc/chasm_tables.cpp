@@ -148,27 +148,6 @@ bool build_axis_tables(int N, int M, int g, int G, double h, int closure, int nk
         }
     }
 
-    // Reduced patch system, rows scaled by 1/6:
-    //   row 0: 2/3, 1/3 | rows 1..m-1: 1/6, 2/3, 1/6 | row m: 1/3, 2/3.
-    const int MF = M + 1;
-    out.fac.assign((size_t)6 * MF, 0.0);
-    for (int slot = 0; slot < 2; ++slot) {
-        const int m = slot == 0 ? M : out.MLAST;
-        double* inv = &out.fac[(size_t)slot * 3 * MF];
-        double* ainv = inv + MF;
-        double* cp = inv + 2 * MF;
-        double prev_cp = 0.0;
-        for (int i = 0; i <= m; ++i) {
-            const double a = (i == 0) ? 0.0 : (i == m ? 1.0 / 3.0 : 1.0 / 6.0);
-            const double c = (i == m) ? 0.0 : (i == 0 ? 1.0 / 3.0 : 1.0 / 6.0);
-            const double den = 2.0 / 3.0 - a * prev_cp;
-            inv[i] = 1.0 / den;
-            ainv[i] = a / den;
-            cp[i] = c / den;
-            prev_cp = cp[i];
-        }
-    }
-
     out.shift.assign(nk, 0);
     out.w.assign((size_t)nk * 4, 0.0);
     for (int i = 0; i < nk; ++i) {

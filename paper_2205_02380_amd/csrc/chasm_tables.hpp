@@ -3,9 +3,9 @@
 // For an axis of N nodes with patches of M cells, ghost width g, spacing h:
 //   stencil  (P+1) rows of width 2G+1: interface slopes d_q = sum_t S[q][t] phi[I_q-G+t]
 //            (PMBC, eqs. 3.4-3.5; rows of the natural-BC inverse, truncated to
-//            |j - I_q| <= g; G >= g is the kernel's compile-time window)
-//   fac      Thomas factors of the reduced patch system for m = M (slot 0) and
-//            m = MLAST (slot 1): inv[i], a_i*inv[i], c'[i] (Sec. 3.1.2 step 5)
+//            |j - I_q| <= g; G >= g is the window).  The kernels carry the same rows
+//            (times h) as compile-time constants; this FP64 copy is the host record
+//            the tests compare them with.
 //   shift/w  per k node: sigma = floor(-alpha), alpha = k dt / h, and the weights
 //            w_r = b_{4-r}(1 - beta) of eq. 3.8, beta = -alpha - sigma.
 #pragma once
@@ -18,7 +18,6 @@ struct AxisTables {
     int N = 0, M = 0, P = 0, MLAST = 0, g = 0, G = 0;
     double h = 0.0;
     std::vector<double> stencil;   // (P+1)*(2G+1)
-    std::vector<double> fac;       // 2*3*(M+1)
     std::vector<int> shift;        // nk
     std::vector<double> w;         // nk*4
 };

@@ -54,6 +54,7 @@ def test_desc_layout_matches_header():
     (lambda d: d.patch.__setitem__(0, 7), chasm.CHASM_EUNSUPPORTED),
     (lambda d: d.nx.__setitem__(0, 20), chasm.CHASM_EUNSUPPORTED),
     (lambda d: setattr(d, "ghost", 9), chasm.CHASM_EUNSUPPORTED),
+    (lambda d: setattr(d, "closure", 1), chasm.CHASM_EUNSUPPORTED),
 ])
 def test_descriptor_validation(mutate, status):
     w = inputs.workload("C2")
@@ -91,40 +92,53 @@ def test_null_arguments_fail_without_device():
 ALPHAS = [0.0, 0.3, -0.3, 0.999, -0.999, 1.0, -1.0, 1.5, -2.5, 3.7, -4.2, 6.0, 0.02, -0.107, -9.5, 11.2, 70.0]
 
 
-@pytest.mark.parametrize("N,M,G", linetwin.SHAPES)
-def test_product_line_algebra_matches_oracle_fp64(N, M, G):
-    """The product's tables (natural-spline slopes by a reduced tridiagonal solve,
-    Thomas factors, eq. 3.8 weights) and its register line routine (reduced patch
-    system, cell values, shifted store), compiled for the host in FP64, reproduce
-    the oracle's dense per-patch solves for every shift class."""
-    rng = np.random.default_rng(N * 100 + M)
+@pytest.mark.parametrize("N,M,G,CL", linetwin.SHAPES)
+def test_product_line_algebra_matches_oracle_fp64(N, M, G, CL):
+    """The product's compile-time PMBC rows and patch factors, its eq. 3.8 weight
+    tables and its register line routine (reduced patch system, cell values, shifted
+    store), compiled for the host in FP64, reproduce the oracle's dense per-patch
+    solves for every shift class."""
+    rng = np.random.default_rng(N * 100 + M + 7 * CL)
     h = 0.7
-    for g in sorted({1, 3, 4, 6, G}):
-        if g > G:
-            continue
-        for closure in (oracle.PMBC, oracle.POLY3):
-            if closure == oracle.POLY3 and g < 3:
-                continue
-            # cubic-exact rows at g = 3 are an exactly determined 4-node Vandermonde
-            # solve: both sides hold them to ~1e-12
-            tol = 1e-13 if closure == oracle.PMBC else 2e-11
-            for a in ALPHAS:
-                phi = rng.standard_normal(N)
-                ref = oracle.line(N, M, g, h, a, phi, closure=closure)
-                got = linetwin.line(True, N, M, G, g, h, closure, a, phi)
-                assert np.max(np.abs(got - ref)) < tol, (g, closure, a)
+    # cubic-exact rows at g = 3 are an exactly determined 4-node Vandermonde solve:
+    # both sides hold them to ~1e-12
+    tol = 1e-13 if CL == 0 else 2e-11
+    for a in ALPHAS:
+        phi = rng.standard_normal(N)
+        ref = oracle.line(N, M, G, h, a, phi, closure=CL)
+        got = linetwin.line(True, N, M, G, CL, h, a, phi)
+        assert np.max(np.abs(got - ref)) < tol, a
 
 
-@pytest.mark.parametrize("N,M,G", [(16, 8, 8), (32, 8, 8), (48, 16, 8), (64, 16, 8)])
+@pytest.mark.parametrize("N,M,G,CL", linetwin.SHAPES)
+def test_compile_time_rows_match_host_tables_and_oracle(N, M, G, CL):
+    """The kernels' compile-time interface rows equal the host FP64 table builder's
+    rows and the oracle's rows (all times h)."""
+    h = 0.35
+    ct = linetwin.rows(N, M, G, CL)
+    host = linetwin.rows(N, M, G, CL, h=h)
+    orc = oracle.stencils(N, M, G, h, CL) * h
+    tol = 1e-14 if CL == 0 else 1e-11
+    assert np.max(np.abs(ct - host)) < tol
+    P = ct.shape[0] - 1
+    for q in range(P + 1):
+        I = q * M if q < P else N - 1
+        for t in range(2 * G + 1):
+            j = I - G + t
+            expect = orc[q, j] if 0 <= j < N else 0.0
+            assert abs(ct[q, t] - expect) < tol
+
+
+@pytest.mark.parametrize("N,M,G", [(16, 8, 4), (32, 8, 6), (48, 16, 8), (64, 16, 8)])
 def test_product_line_algebra_fp32_on_smooth_data(N, M, G):
     """FP32 arithmetic on smooth data stays within 2e-7 of max|f| per sweep."""
     h = 0.7
     x = np.arange(N) * h
     phi = np.exp(-((x - x.mean()) / 3.0) ** 2).astype(np.float32).astype(np.float64)
-    for closure in (oracle.PMBC, oracle.POLY3):
+    for CL in (0, 1):
         for a in (0.3, -0.3, 0.999, -0.999, 1.5, -2.5):
-            ref = oracle.line(N, M, 6, h, a, phi, closure=closure)
-            got = linetwin.line(False, N, M, G, 6, h, closure, a, phi)
+            ref = oracle.line(N, M, G, h, a, phi, closure=CL)
+            got = linetwin.line(False, N, M, G, CL, h, a, phi)
             assert np.max(np.abs(got - ref)) < 2e-7 * np.max(np.abs(phi))
 
 
@@ -135,7 +149,7 @@ def test_product_line_algebra_exact_global_at_full_window():
     rng = np.random.default_rng(5)
     for a in (0.4, -0.6, 1.3):
         phi = rng.standard_normal(N)
-        got = linetwin.line(True, N, M, G, 15, 0.5, oracle.PMBC, a, phi)
+        got = linetwin.line(True, N, M, G, 0, 0.5, a, phi)
         assert np.max(np.abs(got - oracle.global_line(N, 0.5, a, phi))) < 1e-13
 
 

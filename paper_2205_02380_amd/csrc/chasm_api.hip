@@ -99,7 +99,7 @@ struct chasm_advect_s {
     int device = 0;
     const KernelSet* ks = nullptr;
     int schedule = CHASM_SCHED_AUTO;
-    JobDev job{};
+    Work work{};                     // one-job work list of this handle
     FinalizeArgs fin{};
     void* tables = nullptr;          // device block: FP64 tables then FP32 mirror, int shifts
     double* partials = nullptr;      // [rows][NRED]
@@ -230,26 +230,33 @@ static size_t workspace_bytes(const chasm_advect_desc* d, const KernelSet* ks, i
     return b;
 }
 
-// Issue one step's kernels on stream s.
+// Launch one step of schedule sched for the jobs of w on stream s.
+static hipError_t launch_step(const KernelSet* ks, int sched, const Work& w, double* part, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    switch (sched) {
+    case CHASM_SCHED_CUBE:
+        e = ks->cube(w, part, s);
+        break;
+    case CHASM_SCHED_SLAB:
+        e = ks->slab_x1x2(w, nullptr, s);
+        if (e == hipSuccess) e = ks->pencil_x3(w, part, s);
+        break;
+    default:
+        e = ks->slab_x1(w, nullptr, s);
+        if (e == hipSuccess) e = ks->pencil_x2(w, nullptr, s);
+        if (e == hipSuccess) e = ks->pencil_x3(w, part, s);
+        break;
+    }
+    return e;
+}
+
+// Issue one step's kernels of one handle on stream s.
 static hipError_t issue_step(chasm_advect_t h, hipStream_t s)
 {
     const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
     double* part = red ? h->partials : nullptr;
-    hipError_t e = hipSuccess;
-    switch (h->schedule) {
-    case CHASM_SCHED_CUBE:
-        e = h->ks->cube(h->job, part, s);
-        break;
-    case CHASM_SCHED_SLAB:
-        e = h->ks->slab_x1x2(h->job, nullptr, s);
-        if (e == hipSuccess) e = h->ks->pencil_x3(h->job, part, s);
-        break;
-    default:
-        e = h->ks->slab_x1(h->job, nullptr, s);
-        if (e == hipSuccess) e = h->ks->pencil_x2(h->job, nullptr, s);
-        if (e == hipSuccess) e = h->ks->pencil_x3(h->job, part, s);
-        break;
-    }
+    hipError_t e = launch_step(h->ks, h->schedule, h->work, part, s);
     if (e == hipSuccess && red) {
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, h->partials, h->partial_rows, h->fin, h->last, h->hist,
                            h->counter, h->hist_cap, h->desc.nbatch);
@@ -333,12 +340,16 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
 
     const bool f64 = desc->dtype == CHASM_F64;
     char* tbase = static_cast<char*>(h->tables);
-    h->job.f = f_dev;
-    h->job.nitems = nkp * desc->nbatch;
+    JobDev& job = h->work.jobs[0];
+    h->work.njobs = 1;
+    h->work.first[0] = 0;
+    h->work.first[1] = nkp * desc->nbatch;
+    job.f = f_dev;
+    job.nitems = nkp * desc->nbatch;
     for (int a = 0; a < 3; ++a) {
-        h->job.nk[a] = desc->nk[a];
-        h->job.ax[a].w = tbase + (f64 ? tb.off_w64[a] : tb.off_w32[a]);
-        h->job.ax[a].shift = reinterpret_cast<const int*>(tbase + tb.off_shift[a]);
+        job.nk[a] = desc->nk[a];
+        job.ax[a].w = tbase + (f64 ? tb.off_w64[a] : tb.off_w32[a]);
+        job.ax[a].shift = reinterpret_cast<const int*>(tbase + tb.off_shift[a]);
         const double hx = (desc->x_hi[a] - desc->x_lo[a]) / desc->nx[a];
         h->fin.xlo[a] = desc->x_lo[a];
         h->fin.hx[a] = hx;
@@ -383,16 +394,52 @@ chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const i
         if (hs[i]->poisoned) return fail(CHASM_ESTATE, "a handle in the list is poisoned");
         if (nsteps[i] < 0) return fail(CHASM_EINVAL, "nsteps must be >= 0");
         if (hs[i]->stream != hs[0]->stream) return fail(CHASM_EINVAL, "all handles must share one stream");
+        for (int32_t j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return fail(CHASM_EINVAL, "a handle appears twice in the list");
         most = std::max(most, nsteps[i]);
     }
-    // Step-major order: every job advances one step before any job takes the next.
-    for (int32_t s = 0; s < most; ++s)
-        for (int32_t i = 0; i < n; ++i) {
-            if (s >= nsteps[i]) continue;
-            chasm_advect_t h = hs[i];
-            hipError_t e = h->gexec ? hipGraphLaunch(h->gexec, h->stream) : issue_step(h, h->stream);
-            if (e != hipSuccess) return hip_fail(h, e, "step launch");
+    hipStream_t s = n > 0 ? hs[0]->stream : nullptr;
+    // Step-major: every job advances one step before any job takes the next.  Handles
+    // with the same kernels and schedule share one launch per sweep (work lists of at
+    // most kMaxJobs jobs); handles that record per-step diagnostics step on their own.
+    std::vector<chasm_advect_t> live;
+    for (int32_t st = 0; st < most; ++st) {
+        live.clear();
+        for (int32_t i = 0; i < n; ++i)
+            if (st < nsteps[i]) live.push_back(hs[i]);
+        std::vector<bool> done(live.size(), false);
+        for (size_t a = 0; a < live.size(); ++a) {
+            if (done[a]) continue;
+            chasm_advect_t h = live[a];
+            if (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) {
+                hipError_t e = h->gexec ? hipGraphLaunch(h->gexec, s) : issue_step(h, s);
+                if (e != hipSuccess) return hip_fail(h, e, "step launch");
+                done[a] = true;
+                continue;
+            }
+            Work w{};
+            for (size_t b = a; b < live.size() && w.njobs < kMaxJobs; ++b) {
+                chasm_advect_t o = live[b];
+                if (done[b] || o->ks != h->ks || o->schedule != h->schedule ||
+                    (o->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP))
+                    continue;
+                const long long items = o->work.jobs[0].nitems;
+                if (w.first[w.njobs] + items > (1LL << 24)) break;   // keep launch grids small
+                w.jobs[w.njobs] = o->work.jobs[0];
+                w.first[w.njobs + 1] = w.first[w.njobs] + items;
+                ++w.njobs;
+                done[b] = true;
+            }
+            if (w.njobs == 0) {   // a single job larger than the per-launch bound
+                hipError_t e = issue_step(h, s);
+                if (e != hipSuccess) return hip_fail(h, e, "step launch");
+                done[a] = true;
+                continue;
+            }
+            hipError_t e = launch_step(h->ks, h->schedule, w, nullptr, s);
+            if (e != hipSuccess) return hip_fail(h, e, "batched step launch");
         }
+    }
     return CHASM_OK;
 }
 
@@ -400,7 +447,7 @@ chasm_status chasm_advect_diagnostics(chasm_advect_t h, double* out)
 {
     if (!h || !out) return fail(CHASM_EINVAL, "NULL argument");
     if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
-    hipError_t e = h->ks->reduce(h->job, h->partials, h->stream);
+    hipError_t e = h->ks->reduce(h->work, h->partials, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "reduce launch");
     const long long nkp = (long long)h->desc.nk[0] * h->desc.nk[1] * h->desc.nk[2];
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->partials, nkp, h->fin, h->last,

@@ -38,6 +38,25 @@ struct JobDev {
     AxisTabDev ax[3];
 };
 
+// The jobs of one launch, passed by value in the kernel arguments: items of job j are
+// the global items [first[j], first[j+1]).  One handle is a one-job list; several
+// handles with the same kernels share a launch (continuous batching).
+constexpr int kMaxJobs = 24;
+struct Work {
+    int njobs;
+    long long first[kMaxJobs + 1];
+    JobDev jobs[kMaxJobs];
+};
+
+// Job of a global item (uniform across the block) and the item's index in that job.
+__device__ __forceinline__ const JobDev& job_of(const Work& w, long long item, long long& local)
+{
+    int j = 0;
+    while (j + 1 < w.njobs && item >= w.first[j + 1]) ++j;
+    local = item - w.first[j];
+    return w.jobs[j];
+}
+
 // Number of FP64 partials written per block when reducing.
 constexpr int NRED = 8;
 
@@ -201,7 +220,7 @@ __device__ __forceinline__ void write_partials(double (&acc)[5], const int ik[3]
 // flight into VGPRs (N/VW 16-byte buffer loads per lane).  The x3 sweep then runs on
 // the whole cube and the result streams out, with the FP64 partials when asked for.
 template <typename T, int N, int M, int G, int CL, int NT, bool RED>
-__global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ partials)
+__global__ __launch_bounds__(NT) void k_cube(const Work w, double* __restrict__ partials)
 {
     constexpr int PX = N + 1;
     constexpr int VW = Vec16<T>::n;
@@ -221,8 +240,14 @@ __global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ pa
     // recomputed per item instead of being pinned in registers for the whole loop.
     unsigned tid = threadIdx.x;
     V pre[RV];
+    const long long total = w.first[w.njobs];
+    auto cube_of = [&](long long it) {
+        long long local;
+        const JobDev& jb = job_of(w, it, local);
+        return static_cast<T*>(jb.f) + local * (long long)(N * N * N);
+    };
     auto fetch = [&](long long it, int round) {
-        const Buf b(static_cast<const T*>(job.f) + it * (long long)(N * N * N), CUBE_BYTES);
+        const Buf b(cube_of(it), CUBE_BYTES);
         static_for<0, RV>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             pre[q] = b.template load16<T>(tid * 16u, (uint32_t)((round * RV + q) * NT * 16));
@@ -241,7 +266,7 @@ __global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ pa
     };
 
     long long item = blockIdx.x;
-    if (item >= job.nitems) return;
+    if (item >= total) return;
     fetch(item, 0);
     fill(0);
     // The loop is rotated: an item's first round is written to LDS at the end of the
@@ -254,8 +279,10 @@ __global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ pa
         const unsigned vbase = (tid * VW / N) * PX + (tid * VW) % N;
         const unsigned plane_t = tid / N, lane_t = tid % N;
         const long long next = item + gridDim.x;
+        long long local;
+        const JobDev& job = job_of(w, item, local);
         int ik[3];
-        item_k(job, item, ik);
+        item_k(job, local, ik);
         int sig0, sig1;
         const auto k0 = axis_coef<T>(job, 0, ik[0], sig0);
         const auto k1 = axis_coef<T>(job, 1, ik[1], sig1);
@@ -265,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ pa
             if (r > 0) fill(r);
             __syncthreads();
             if (r + 1 < ROUNDS) fetch(item, r + 1);
-            else if (next < job.nitems) fetch(next, 0);
+            else if (next < total) fetch(next, 0);
             const unsigned plane = r * PL + plane_t;
             {   // x1: row (x2 = lane_t) of this thread's plane
                 T* row = lds + (plane * N + lane_t) * PX;
@@ -339,13 +366,13 @@ __global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ pa
             write_partials<NT>(acc, ik, partials + item * NRED);
         }
         __syncthreads();
-        if (next < job.nitems) fill(0);
-        const Buf b(static_cast<T*>(job.f) + item * (long long)(N * N * N), CUBE_BYTES);
+        if (next < total) fill(0);
+        const Buf b(static_cast<T*>(job.f) + local * (long long)(N * N * N), CUBE_BYTES);
         static_for<0, NV / NT>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             b.template store16<T>(out[q], tid * 16u, (uint32_t)(q * NT * 16));
         });
-        if (next >= job.nitems) break;
+        if (next >= total) break;
         item = next;
     }
 }
@@ -354,7 +381,7 @@ __global__ __launch_bounds__(NT) void k_cube(JobDev job, double* __restrict__ pa
 // S x3-slabs (N x N each) per block in LDS: x1 sweep, then (X2 = true) the x2 sweep
 // stored straight to global memory.  Block = S*N threads, one line each.
 template <typename T, int N, int M, int G, int CL, int S, bool X2>
-__global__ __launch_bounds__(S * N) void k_slab(JobDev job)
+__global__ __launch_bounds__(S * N) void k_slab(const Work w)
 {
     constexpr int PX = N + 1;
     constexpr int NT = S * N;
@@ -364,7 +391,8 @@ __global__ __launch_bounds__(S * N) void k_slab(JobDev job)
     __shared__ T lds[S * N * PX];
 
     constexpr int BPI = N / S;                     // blocks per item
-    const long long item = blockIdx.x / BPI;
+    long long item;
+    const JobDev& job = job_of(w, blockIdx.x / BPI, item);
     const int slab0 = (blockIdx.x % BPI) * S;
     int ik[3];
     item_k(job, item, ik);
@@ -422,11 +450,12 @@ __global__ __launch_bounds__(S * N) void k_slab(JobDev job)
 // One line per lane along axis AXIS (1: x2, 2: x3), NT lines per block; NT divides
 // N*N so a block never straddles two items.  Optional fused FP64 partials.
 template <typename T, int N, int M, int G, int CL, int NT, int AXIS, bool RED>
-__global__ __launch_bounds__(NT) void k_pencil(JobDev job, double* __restrict__ partials)
+__global__ __launch_bounds__(NT) void k_pencil(const Work w, double* __restrict__ partials)
 {
     static_assert((N * N) % NT == 0, "block must tile the lines of one item");
     constexpr int BPI = N * N / NT;
-    const long long item = blockIdx.x / BPI;
+    long long item;
+    const JobDev& job = job_of(w, blockIdx.x / BPI, item);
     const int L = (blockIdx.x % BPI) * NT + threadIdx.x;
     int ik[3];
     item_k(job, item, ik);
@@ -475,11 +504,12 @@ __global__ __launch_bounds__(NT) void k_pencil(JobDev job, double* __restrict__ 
 // ---------------------------------------------------------------------------
 // Diagnostics of the current field, one item per block.
 template <typename T, int N, int NT>
-__global__ __launch_bounds__(NT) void k_reduce_field(JobDev job, double* __restrict__ partials)
+__global__ __launch_bounds__(NT) void k_reduce_field(const Work w, double* __restrict__ partials)
 {
     constexpr int VW = Vec16<T>::n;
     using V = typename Vec16<T>::type;
-    const long long item = blockIdx.x;
+    long long item;
+    const JobDev& job = job_of(w, blockIdx.x, item);
     int ik[3];
     item_k(job, item, ik);
     const V* __restrict__ src = reinterpret_cast<const V*>(static_cast<const T*>(job.f) + item * (long long)(N * N * N));
@@ -499,7 +529,7 @@ __global__ __launch_bounds__(NT) void k_reduce_field(JobDev job, double* __restr
         acc[3] = fma((double)(row % N), s, acc[3]);
         acc[4] = fma((double)(row / N), s, acc[4]);
     }
-    write_partials<NT>(acc, ik, partials + item * NRED);
+    write_partials<NT>(acc, ik, partials + (long long)blockIdx.x * NRED);
 }
 
 struct FinalizeArgs {

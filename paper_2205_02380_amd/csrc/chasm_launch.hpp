@@ -42,14 +42,15 @@ int resident_blocks(K k, int threads)
 }
 
 template <typename T, int N, int M, int G, int CL>
-hipError_t launch_cube(const JobDev& job, double* partials, hipStream_t s)
+hipError_t launch_cube(const Work& w, double* partials, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     if constexpr (Lc::cube_fits) {
         auto launch = [&](auto k) {
             const long long res = resident_blocks(k, Lc::cube_nt);
-            const unsigned grid = (unsigned)(res > 0 && res < job.nitems ? res : job.nitems);
-            hipLaunchKernelGGL(k, dim3(grid), dim3(Lc::cube_nt), 0, s, job, partials);
+            const long long items = w.first[w.njobs];
+            const unsigned grid = (unsigned)(res > 0 && res < items ? res : items);
+            hipLaunchKernelGGL(k, dim3(grid), dim3(Lc::cube_nt), 0, s, w, partials);
             return hipGetLastError();
         };
         return partials ? launch(k_cube<T, N, M, G, CL, Lc::cube_nt, true>)
@@ -60,34 +61,34 @@ hipError_t launch_cube(const JobDev& job, double* partials, hipStream_t s)
 }
 
 template <typename T, int N, int M, int G, int CL, bool X2>
-hipError_t launch_slab(const JobDev& job, double*, hipStream_t s)
+hipError_t launch_slab(const Work& w, double*, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     constexpr int S = Lc::slab_s;
-    const unsigned grid = (unsigned)(job.nitems * (N / S));
-    hipLaunchKernelGGL((k_slab<T, N, M, G, CL, S, X2>), dim3(grid), dim3(S * N), 0, s, job);
+    const unsigned grid = (unsigned)(w.first[w.njobs] * (N / S));
+    hipLaunchKernelGGL((k_slab<T, N, M, G, CL, S, X2>), dim3(grid), dim3(S * N), 0, s, w);
     return hipGetLastError();
 }
 
 template <typename T, int N, int M, int G, int CL, int AXIS>
-hipError_t launch_pencil(const JobDev& job, double* partials, hipStream_t s)
+hipError_t launch_pencil(const Work& w, double* partials, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     constexpr int NT = Lc::pencil_nt;
-    const unsigned grid = (unsigned)(job.nitems * (N * N / NT));
+    const unsigned grid = (unsigned)(w.first[w.njobs] * (N * N / NT));
     if (partials)
-        hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, AXIS, true>), dim3(grid), dim3(NT), 0, s, job, partials);
+        hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, AXIS, true>), dim3(grid), dim3(NT), 0, s, w, partials);
     else
-        hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, AXIS, false>), dim3(grid), dim3(NT), 0, s, job, partials);
+        hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, AXIS, false>), dim3(grid), dim3(NT), 0, s, w, partials);
     return hipGetLastError();
 }
 
 template <typename T, int N>
-hipError_t launch_reduce(const JobDev& job, double* partials, hipStream_t s)
+hipError_t launch_reduce(const Work& w, double* partials, hipStream_t s)
 {
     using Lc = Launch<T, N>;
-    hipLaunchKernelGGL((k_reduce_field<T, N, Lc::reduce_nt>), dim3((unsigned)job.nitems), dim3(Lc::reduce_nt), 0, s,
-                       job, partials);
+    hipLaunchKernelGGL((k_reduce_field<T, N, Lc::reduce_nt>), dim3((unsigned)w.first[w.njobs]), dim3(Lc::reduce_nt), 0,
+                       s, w, partials);
     return hipGetLastError();
 }
 

@@ -9,11 +9,11 @@
 
 namespace chasm {
 
-struct JobDev;
+struct Work;
 
-// partials: FP64 block partials (nullptr: no reduction).  Grids are derived from
-// job.nitems.  Returns the launch status.
-using LaunchFn = hipError_t (*)(const JobDev& job, double* partials, hipStream_t stream);
+// partials: FP64 block partials (nullptr: no reduction).  Grids are derived from the
+// work list's item count.  Returns the launch status.
+using LaunchFn = hipError_t (*)(const Work& w, double* partials, hipStream_t stream);
 
 struct KernelSet {
     int dtype;              // 0 float, 1 double

@@ -260,11 +260,15 @@ def test_batch_equals_single_runs_bitwise():
 
 
 def test_step_many_equals_individual_runs():
+    """Handles with the same kernels share one launch per sweep (a work list of jobs with
+    their own fields, dt and k grids); each result equals the job run alone, bitwise."""
     jobs = []
-    for i, (n, nk, kr) in enumerate(((16, 8, 2.0), (24, 12, 3.0), (32, 16, 4.0))):
+    specs = [(16, 8, 2.0, 0.01, 5), (16, 8, 2.0, 0.05, 7), (24, 12, 3.0, 0.02, 9), (16, 8, 2.0, 0.02, 3),
+             (32, 16, 4.0, 0.05, 4), (24, 12, 3.0, 0.01, 6), (16, 8, 2.0, 0.02, 8)]
+    for i, (n, nk, kr, dt, steps) in enumerate(specs):
         grid = inputs.cubic_grid(n, n * 0.5, nk, kr)
         jobs.append((grid, inputs.gaussian_field(grid, inputs.random_packets(3, 70 + i), dtype=torch.float32),
-                     (5, 9, 3)[i], (0.01, 0.02, 0.05)[i]))
+                     steps, dt))
     fs = [j[1].to(DEV) for j in jobs]
     advs = [chasm.Advect(f, j[0], 8, 6, j[3]) for f, j in zip(fs, jobs)]
     chasm.step_many(advs, [j[2] for j in jobs])

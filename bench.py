@@ -14,6 +14,12 @@ sample of k-points (cpu_baseline), whose result at those k-points also gives the
 error of the timed GPU run.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Other workloads (one JSON line each): --workload C3 (48^3 x 24^3, autotuned patch /
+ghost / schedule, FP64 mass and L2 recorded every step), --workload C4 (64^3 x 32^3,
+one GPU's share of a paper-scale grid, 34 GB per copy), --workload serving (200
+Poisson-arriving requests of mixed grids under a 200 GB HBM budget, continuous
+batching; p50/p99 step latency and aggregate point-updates/s).
 """
 import argparse
 import hashlib
@@ -65,6 +71,115 @@ def time_steps(adv, torch, steps, stream):
     return ev[0].elapsed_time(ev[steps]) / 1e3, per
 
 
+METRIC = "6-D point-updates/s FP32 vs FP64 plain at <=1e-5 rel err; p50/p99 step latency"
+
+
+def oracle_sample(g, w, cubes, kidx, nst):
+    """cpu_baseline leg: the FP64 oracle on a k-point sample, timed on the host cores."""
+    import oracle
+    nthreads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    ref = oracle.advect6d(cubes, g.nx, g.hx, g.nk, g.k_lo, g.hk, w.patch, w.ghost, w.dt, nst, kidx=kidx,
+                          nthreads=nthreads)
+    tc = time.perf_counter() - t0
+    cpu = {"value": len(kidx) * g.cube * nst / tc, "unit": "point-updates/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"{len(kidx)} seeded k-points x {g.cube} x-points x {nst} steps "
+                     f"({tc:.1f} s wall, FP64, OpenMP over k-points)"}
+    return cpu, ref
+
+
+def bench_large(args, name):
+    """C3 / C4: one large FP32 job, graph-replayed steps, per-step FP64 diagnostics."""
+    import dataclasses
+
+    import torch
+    from paper_2205_02380_amd import autotune, chasm, inputs
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    w = inputs.workload(name)
+    tuning = None
+    if name == "C3" and not args.no_tune:
+        res = autotune.tune(w.grid, w.dt, w.packets, steps=5, tol=1e-5,
+                            log=lambda m: print(m, file=sys.stderr, flush=True))
+        b = res["best"]
+        tuning = {"best": b, "candidates": len(res["candidates"]),
+                  "table": [[c["patch"], c["ghost"], c["schedule"], round(c["ms_per_step"], 3),
+                             float("%.3g" % c["deviation"])] for c in res["candidates"]]}
+        w = dataclasses.replace(w, patch=(b["patch"],) * 3, ghost=b["ghost"])
+        sched = b["schedule"]
+    else:
+        sched = "auto"
+    g = w.grid
+    f = torch.empty(g.shape(), dtype=torch.float32, device=dev)
+    coef, gx, gk = inputs.packet_factors(g, w.packets)
+    inputs.fill_separable(f, coef, gx, gk)
+    kidx = inputs.k_sample(g, args.cpu_kpoints / g.nkpts, 40)
+    start = np.stack([f[i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in kidx])
+    steps = args.steps
+    adv = chasm.Advect(f, g, w.patch, w.ghost, w.dt, schedule=sched, graph=True, reduce_each_step=True,
+                       history_cap=steps + args.warmup, stream=stream)
+    sched = adv.schedule
+    adv.step(args.warmup)
+    torch.cuda.synchronize()
+    total_s, per = time_steps(adv, torch, steps, stream)
+    hist = adv.history(steps + args.warmup)
+    adv.close()
+    got = np.stack([f[i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in kidx])
+    del f
+    torch.cuda.empty_cache()
+    value = g.points * steps / total_s
+    bpp = 8.0 if sched == "cube" else (16.0 if sched == "slab" else 24.0)
+    achieved = bpp * g.points / (float(per.mean()) / 1e3) / 1e9
+    cpu = err = None
+    if not args.no_cpu:
+        nst = min(args.warmup + steps, args.cpu_steps) if args.cpu_steps else args.warmup + steps
+        cpu, ref = oracle_sample(g, w, start, kidx, nst)
+        if nst == args.warmup + steps:
+            err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    m0 = hist[0, 0, 0]
+    return {
+        "metric": METRIC, "value": value, "unit": "point-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": total_s * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded Gaussian-packet mixture, generated on the GPU)",
+        "config": {"workload": f"{w.name}: {g.nx[0]}^3 x by {g.nk[0]}^3 k, {g.points} points, patch {w.patch[0]}, "
+                               f"ghost {w.ghost}, dt {w.dt}, FP32, one job, FP64 mass/L2 every step",
+                   "schedule": sched, "graph": True},
+        "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
+                            "mean": float(per.mean())},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole step (" + ("k_cube" if sched == "cube" else "k_slab + k_pencil") + ")",
+                     "alg_bytes_per_point_update": bpp},
+        "mass_drift": float(abs(hist[-1, 0, 0] - m0) / abs(m0)), "l2_last": float(hist[-1, 0, 1]),
+        "autotune": tuning, "err_vs_oracle": err, "cpu_baseline": cpu,
+    }
+
+
+def bench_serving(args):
+    import torch
+    from paper_2205_02380_amd import inputs, serve
+    trace = inputs.serving_trace()
+    be = serve.ChasmBackend()
+    # warm the kernels of every shape class once
+    warm = [inputs.Request(-1 - i, 0.0, gr, 1, 0.02, inputs.random_packets(1, 1)) for i, gr in
+            enumerate(inputs.SERVING_SHAPES)]
+    serve.Server(be, budget_bytes=200e9, max_active=64).run(warm)
+    torch.cuda.synchronize()
+    rep = serve.Server(be, budget_bytes=200e9, max_active=64).run(trace)
+    d = rep.as_dict()
+    return {
+        "metric": METRIC, "value": rep.throughput, "unit": "point-updates/s", "n_gpus": 1, "steps": rep.ticks,
+        "warmup": len(warm), "ms_per_step": rep.makespan_s * 1e3 / max(rep.ticks, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded request trace and Gaussian-packet fields)",
+        "config": {"workload": "serving: 200 requests, Poisson 20/s, grids {16^3x8^3, 24^3x12^3, 32^3x16^3, "
+                               "48^3x16^3}, steps U[10,200], dt {0.01,0.02,0.05}, 200 GB HBM budget, "
+                               "continuous batching", "patch": 8, "ghost": 6},
+        "step_latency_ms": {"p50": d["p50_step_ms"], "p99": d["p99_step_ms"]},
+        "serving": d, "roofline": None, "cpu_baseline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +189,9 @@ def main():
     ap.add_argument("--cpu-kpoints", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "serving"])
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain device copy of 1 GiB (the reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -88,6 +206,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload in ("C3", "C4"):
+        print(json.dumps(bench_large(args, args.workload)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(bench_serving(args)), flush=True)
+        return
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     if args.calibrate_copy:
@@ -143,22 +267,12 @@ def main():
     cpu = None
     err = None
     if not args.no_cpu:
-        import oracle
-        nthreads = len(os.sched_getaffinity(0))
-        nst = args.warmup + args.steps
-        t0 = time.perf_counter()
-        ref = oracle.advect6d(start_cubes, g.nx, g.hx, g.nk, g.k_lo, g.hk, w.patch, w.ghost, w.dt, nst,
-                              kidx=kidx, nthreads=nthreads)
-        tc = time.perf_counter() - t0
-        cpu = {"value": len(kidx) * g.cube * nst / tc, "unit": "point-updates/s", "cores": nthreads,
-               "kind": "oracle",
-               "sample": f"{len(kidx)} seeded k-points x {g.cube} x-points x {nst} steps "
-                         f"({tc:.1f} s wall, FP64, OpenMP over k-points)"}
+        cpu, ref = oracle_sample(g, w, start_cubes, kidx, args.warmup + args.steps)
         err = float(np.max(np.abs(gpu_cubes - ref)) / np.max(np.abs(ref)))
 
     traffic = measured_traffic(kernel, "C2")
     line = {
-        "metric": "6-D point-updates/s FP32 vs FP64 plain at <=1e-5 rel err; p50/p99 step latency",
+        "metric": METRIC,
         "value": value,
         "unit": "point-updates/s",
         "n_gpus": 1,

@@ -1,0 +1,126 @@
+"""Autotuner: pick patch size, ghost width and kernel schedule for a grid.
+
+Every candidate (patch M, ghost g, schedule) that has compiled kernels is timed on the
+workload's own field (HIP events around graph-replayed steps) and its result after the
+tuning steps is compared with the most accurate candidate (the largest ghost width,
+then the largest patch): the PMBC truncation error shrinks like |sqrt3 - 2|^g, so a
+smaller g is faster to compute but drifts from the untruncated spline.  The winner is
+the fastest candidate whose result stays within `tol` (relative to max|f|) of that
+reference.  Results can be cached in a JSON file keyed by the grid and dt.
+
+Host logic only: every step runs through the C ABI.  Parity of each compiled (M, g)
+with the FP64 oracle is the test suite's job, not the tuner's.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+from typing import Dict, List, Optional, Sequence
+
+from . import chasm, inputs
+
+
+def candidates(grid: inputs.Grid, dt: float, patches: Sequence[int], ghosts: Sequence[int],
+               schedules: Sequence[str]) -> List[dict]:
+    out = []
+    for M in patches:
+        for g in ghosts:
+            for sc in schedules:
+                d = chasm.make_desc(grid, M, g, dt, schedule=sc)
+                try:
+                    chasm.chasm_advect_workspace_bytes(d)
+                except chasm.ChasmError:
+                    continue
+                out.append({"patch": M, "ghost": g, "schedule": sc})
+    return out
+
+
+def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 16), ghosts=(4, 6, 8),
+         schedules=("cube", "slab", "plain"), steps: int = 5, warmup: int = 2, tol: float = 1e-5,
+         device: str = "cuda:0", log=None) -> dict:
+    import torch
+    dev = torch.device(device)
+    stream = torch.cuda.current_stream(dev)
+    cands = candidates(grid, dt, patches, ghosts, schedules)
+    if not cands:
+        raise ValueError("no compiled kernels for this grid")
+    f0 = torch.empty(grid.shape(), dtype=torch.float32, device=dev)
+    coef, gx, gk = inputs.packet_factors(grid, packets)
+    inputs.fill_separable(f0, coef, gx, gk)
+    work = torch.empty_like(f0)
+    # most accurate first: largest ghost width, then largest patch
+    cands.sort(key=lambda c: (-c["ghost"], -c["patch"], c["schedule"]))
+    ref = None
+    scale = None
+    for c in cands:
+        work.copy_(f0)
+        adv = chasm.Advect(work, grid, c["patch"], c["ghost"], dt, schedule=c["schedule"], graph=True,
+                           stream=stream)
+        adv.step(warmup)
+        torch.cuda.synchronize()
+        work.copy_(f0)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        adv.step(steps)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        adv.close()
+        c["ms_per_step"] = ev[0].elapsed_time(ev[1]) / steps
+        c["point_updates_per_s"] = grid.points / (c["ms_per_step"] * 1e-3)
+        if ref is None:
+            ref = work.clone()
+            scale = float(ref.abs().max())
+            c["deviation"] = 0.0
+        else:
+            c["deviation"] = float((work - ref).abs().max()) / scale
+        c["ok"] = c["deviation"] <= tol
+        if log:
+            log(f"  M={c['patch']:2d} g={c['ghost']} {c['schedule']:5s} {c['ms_per_step']:8.3f} ms/step "
+                f"dev={c['deviation']:.2e}{'' if c['ok'] else '  (over tol)'}")
+    del work, f0, ref
+    torch.cuda.empty_cache()
+    ok = [c for c in cands if c["ok"]]
+    best = min(ok, key=lambda c: c["ms_per_step"])
+    return {"grid": {"nx": list(grid.nx), "nk": list(grid.nk)}, "dt": dt, "tol": tol, "steps": steps,
+            "candidates": cands, "best": best}
+
+
+def cache_key(grid: inputs.Grid, dt: float) -> str:
+    return f"nx{grid.nx[0]}_nk{grid.nk[0]}x{grid.nk[1]}x{grid.nk[2]}_dt{dt:g}"
+
+
+def load_cache(path: str) -> Dict[str, dict]:
+    if path and os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    return {}
+
+
+def lookup(path: str, grid: inputs.Grid, dt: float) -> Optional[dict]:
+    return load_cache(path).get(cache_key(grid, dt))
+
+
+def store(path: str, grid: inputs.Grid, dt: float, result: dict) -> None:
+    c = load_cache(path)
+    c[cache_key(grid, dt)] = result
+    with open(path, "w") as fh:
+        json.dump(c, fh, indent=1)
+
+
+def main():
+    ap = argparse.ArgumentParser(description="autotune patch / ghost / schedule for a workload")
+    ap.add_argument("--workload", default="C3")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--cache", default="")
+    args = ap.parse_args()
+    w = inputs.workload(args.workload)
+    res = tune(w.grid, w.dt, w.packets, steps=args.steps, tol=args.tol, log=print)
+    print(json.dumps(res["best"]))
+    if args.cache:
+        store(args.cache, w.grid, w.dt, res)
+
+
+if __name__ == "__main__":
+    main()

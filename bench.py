@@ -60,6 +60,16 @@ def measured_traffic(kernel: str, workload: str):
     return e.get("hbm_bytes_per_launch")
 
 
+def step_traffic(sched: str, workload: str):
+    """Measured HBM bytes of one step: the cube kernel, or the slab + pencil pair."""
+    if sched == "cube":
+        return measured_traffic("k_cube", workload)
+    if sched == "slab":
+        a, b = measured_traffic("k_slab", workload), measured_traffic("k_pencil", workload)
+        return None if a is None or b is None else a + b
+    return None
+
+
 def time_steps(adv, torch, steps, stream):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record(stream)
@@ -147,7 +157,7 @@ def bench_large(args, name):
         "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
                             "mean": float(per.mean())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": step_traffic(sched, name),
                      "kernel": "whole step (" + ("k_cube" if sched == "cube" else "k_slab + k_pencil") + ")",
                      "alg_bytes_per_point_update": bpp},
         "mass_drift": float(abs(hist[-1, 0, 0] - m0) / abs(m0)), "l2_last": float(hist[-1, 0, 1]),
@@ -206,12 +216,6 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    if args.workload in ("C3", "C4"):
-        print(json.dumps(bench_large(args, args.workload)), flush=True)
-        return
-    if args.workload == "serving":
-        print(json.dumps(bench_serving(args)), flush=True)
-        return
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     if args.calibrate_copy:
@@ -222,6 +226,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload in ("C3", "C4"):
+        print(json.dumps(bench_large(args, args.workload)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(bench_serving(args)), flush=True)
+        return
     w = inputs.workload("C2")
     g = w.grid
     points = g.points

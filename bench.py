@@ -70,6 +70,25 @@ def step_traffic(sched: str, workload: str):
     return None
 
 
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+    """Measured device copy rate (read + write bytes / time) of a plain 1 GiB copy: the
+    practical HBM ceiling of this machine, reported beside the published peak."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (a.elapsed_time(b) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def time_steps(adv, torch, steps, stream):
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record(stream)
@@ -107,6 +126,7 @@ def bench_large(args, name):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     w = inputs.workload(name)
+    copy_gbs = copy_bandwidth(torch, dev)
     tuning = None
     if name == "C3" and not args.no_tune:
         res = autotune.tune(w.grid, w.dt, w.packets, steps=5, tol=1e-5,
@@ -159,7 +179,8 @@ def bench_large(args, name):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": step_traffic(sched, name),
                      "kernel": "whole step (" + ("k_cube" if sched == "cube" else "k_slab + k_pencil") + ")",
-                     "alg_bytes_per_point_update": bpp},
+                     "alg_bytes_per_point_update": bpp, "measured_copy_GBs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs},
         "mass_drift": float(abs(hist[-1, 0, 0] - m0) / abs(m0)), "l2_last": float(hist[-1, 0, 1]),
         "autotune": tuning, "err_vs_oracle": err, "cpu_baseline": cpu,
     }
@@ -235,6 +256,7 @@ def main():
     w = inputs.workload("C2")
     g = w.grid
     points = g.points
+    copy_gbs = copy_bandwidth(torch, dev)
 
     # ---- FP32, cube schedule, graph replay ------------------------------------------
     f = torch.empty(g.shape(), dtype=torch.float32, device=dev)
@@ -300,7 +322,8 @@ def main():
                             "mean": float(per.mean())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
-                     "alg_bytes_per_launch": bytes_alg},
+                     "alg_bytes_per_launch": bytes_alg, "measured_copy_GBs": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs},
         "fp64_plain": None if value64 is None else {
             "value": value64, "unit": "point-updates/s", "ms_per_step": t64 * 1e3 / args.fp64_steps,
             "schedule": "plain (3 launches/step, eager)", "alg_bytes_per_point_update": 48},

@@ -46,6 +46,33 @@ static const KernelSet* find_kernels(int dtype, int N, int M, int g, int closure
 }
 
 // ---------------------------------------------------------------------------
+// First stage of a long partial-row reduction: block (c, b) sums its fixed chunk of
+// the rows of batch member b (strided over the threads, then a tree), so the result
+// does not depend on timing.  The finalize kernel then reduces FOLD_CHUNKS rows.
+constexpr int FOLD_CHUNKS = 256;
+constexpr long long FOLD_MIN_ROWS = 4096;
+
+__global__ __launch_bounds__(256) void k_fold(const double* __restrict__ in, long long rows, double* __restrict__ out)
+{
+    __shared__ double red[256][NRED];
+    const long long per = (rows + gridDim.x - 1) / gridDim.x;
+    const long long r0 = (long long)blockIdx.x * per;
+    const long long r1 = r0 + per < rows ? r0 + per : rows;
+    const double* p = in + (long long)blockIdx.y * rows * NRED;
+    double acc[NRED];
+    for (int v = 0; v < NRED; ++v) acc[v] = 0.0;
+    for (long long r = r0 + threadIdx.x; r < r1; r += 256)
+        for (int v = 0; v < NRED; ++v) acc[v] += p[r * NRED + v];
+    for (int v = 0; v < NRED; ++v) red[threadIdx.x][v] = acc[v];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int v = 0; v < NRED; ++v) red[threadIdx.x][v] += red[threadIdx.x + w][v];
+        __syncthreads();
+    }
+    if (threadIdx.x < NRED) out[((long long)blockIdx.y * gridDim.x + blockIdx.x) * NRED + threadIdx.x] = red[0][threadIdx.x];
+}
+
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, long long rows_per_batch,
                                                   FinalizeArgs a, double* __restrict__ out,
                                                   double* __restrict__ hist, int* __restrict__ counter,
@@ -103,6 +130,7 @@ struct chasm_advect_s {
     FinalizeArgs fin{};
     void* tables = nullptr;          // device block: FP64 tables then FP32 mirror, int shifts
     double* partials = nullptr;      // [rows][NRED]
+    double* fold = nullptr;          // [nbatch][FOLD_CHUNKS][NRED]
     long long partial_rows = 0;      // rows per batch member when reducing each step
     double* last = nullptr;          // [nbatch][NRED]
     double* hist = nullptr;          // [cap][nbatch][NRED]
@@ -225,6 +253,7 @@ static size_t workspace_bytes(const chasm_advect_desc* d, const KernelSet* ks, i
     const int cap = d->history_cap > 0 ? d->history_cap : 1024;
     size_t b = table_bytes + 256;
     b += (size_t)rows * NRED * sizeof(double) + 256;
+    b += (size_t)d->nbatch * FOLD_CHUNKS * NRED * sizeof(double) + 256;
     b += (size_t)d->nbatch * NRED * sizeof(double) + 256;
     if (d->flags & CHASM_FLAG_REDUCE_EACH_STEP) b += (size_t)cap * d->nbatch * NRED * sizeof(double) + 256 + 256;
     return b;
@@ -252,16 +281,28 @@ static hipError_t launch_step(const KernelSet* ks, int sched, const Work& w, dou
 }
 
 // Issue one step's kernels of one handle on stream s.
+// Reduce `rows` partial rows per batch member into the diagnostics (and, when
+// `record`, the next history slot): one block directly, or a fold stage first.
+static hipError_t launch_finalize(chasm_advect_s* h, long long rows, bool record, hipStream_t s)
+{
+    const double* src = h->partials;
+    const int nb = h->desc.nbatch;
+    if (rows > FOLD_MIN_ROWS) {
+        hipLaunchKernelGGL(k_fold, dim3(FOLD_CHUNKS, nb), dim3(256), 0, s, h->partials, rows, h->fold);
+        src = h->fold;
+        rows = FOLD_CHUNKS;
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, src, rows, h->fin, h->last, record ? h->hist : nullptr,
+                       record ? h->counter : nullptr, record ? h->hist_cap : 1, nb);
+    return hipGetLastError();
+}
+
 static hipError_t issue_step(chasm_advect_t h, hipStream_t s)
 {
     const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
     double* part = red ? h->partials : nullptr;
     hipError_t e = launch_step(h->ks, h->schedule, h->work, part, s);
-    if (e == hipSuccess && red) {
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, h->partials, h->partial_rows, h->fin, h->last, h->hist,
-                           h->counter, h->hist_cap, h->desc.nbatch);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess && red) e = launch_finalize(h, h->partial_rows, true, s);
     return e;
 }
 
@@ -326,6 +367,8 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
     const long long rows = std::max(h->partial_rows, nkp) * desc->nbatch;
     if (hipMalloc((void**)&h->partials, (size_t)rows * NRED * sizeof(double)) != hipSuccess)
         return bail(CHASM_ENOMEM, "hipMalloc(partials) failed");
+    if (hipMalloc((void**)&h->fold, (size_t)desc->nbatch * FOLD_CHUNKS * NRED * sizeof(double)) != hipSuccess)
+        return bail(CHASM_ENOMEM, "hipMalloc(fold) failed");
     if (hipMalloc((void**)&h->last, (size_t)desc->nbatch * NRED * sizeof(double)) != hipSuccess)
         return bail(CHASM_ENOMEM, "hipMalloc(diagnostics) failed");
     if (desc->flags & CHASM_FLAG_REDUCE_EACH_STEP) {
@@ -450,9 +493,7 @@ chasm_status chasm_advect_diagnostics(chasm_advect_t h, double* out)
     hipError_t e = h->ks->reduce(h->work, h->partials, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "reduce launch");
     const long long nkp = (long long)h->desc.nk[0] * h->desc.nk[1] * h->desc.nk[2];
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->stream, h->partials, nkp, h->fin, h->last,
-                       (double*)nullptr, (int*)nullptr, 1, h->desc.nbatch);
-    e = hipGetLastError();
+    e = launch_finalize(h, nkp, false, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "finalize launch");
     e = hipMemcpyAsync(out, h->last, (size_t)h->desc.nbatch * NRED * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "diagnostics copy");
@@ -519,6 +560,7 @@ chasm_status chasm_advect_destroy(chasm_advect_t h)
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->tables) hipFree(h->tables);
     if (h->partials) hipFree(h->partials);
+    if (h->fold) hipFree(h->fold);
     if (h->last) hipFree(h->last);
     if (h->hist) hipFree(h->hist);
     if (h->counter) hipFree(h->counter);

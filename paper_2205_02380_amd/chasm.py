@@ -249,3 +249,29 @@ class Advect:
 
 def step_many(advects: Sequence[Advect], nsteps: Sequence[int]) -> None:
     chasm_advect_step_many([a.h for a in advects], nsteps)
+
+
+def supported(grid: Grid, patch, ghost: int, dt: float = 0.0, dtype: str = "f32", closure: str = "pmbc",
+              schedule: str = "auto") -> bool:
+    """True when the library has kernels for this grid / patch / ghost / dtype / closure
+    and schedule (asks the library's own descriptor validation; no device work)."""
+    try:
+        chasm_advect_workspace_bytes(make_desc(grid, patch, ghost, dt, dtype, closure, schedule=schedule))
+        return True
+    except ChasmError:
+        return False
+
+
+def compiled_shapes(sizes=(8, 16, 24, 32, 48, 64)) -> list:
+    """Every (dtype, N, M, ghost, closure) with compiled kernels, for cubic x-grids of N
+    nodes per axis (found through descriptor validation)."""
+    out = []
+    for n in sizes:
+        grid = Grid((n, n, n), (0.0,) * 3, (float(n),) * 3, (1, 1, 1), (0.0,) * 3, (1.0,) * 3)
+        for dt in ("f32", "f64"):
+            for cl in ("pmbc", "poly3"):
+                for m in range(2, n + 1):
+                    for g in range(1, n):
+                        if supported(grid, m, g, 0.0, dt, cl):
+                            out.append((dt, n, m, g, cl))
+    return out

@@ -305,8 +305,11 @@ def test_device_errors():
 
 
 # --------------------------------------------------------------------------- large grids
-def _large_case(name, steps, nsample, seed):
+def _large_case(name, steps, nsample, seed, patch=None, ghost=None):
+    import dataclasses
     w = inputs.workload(name)
+    if patch is not None:
+        w = dataclasses.replace(w, patch=(patch,) * 3, ghost=ghost)
     g = w.grid
     say(f"{name}: generating {g.points:.3e} points on the GPU")
     f = torch.empty(g.shape(), dtype=torch.float32, device=DEV)
@@ -343,6 +346,14 @@ def _large_case(name, steps, nsample, seed):
 
 def test_c3_slab_schedule_10_steps():
     _large_case("C3", 10, 6, 30)
+
+
+@pytest.mark.parametrize("M", [8, 12])
+@pytest.mark.parametrize("g", [4, 6, 8])
+def test_c3_every_tuning_candidate(M, g):
+    """The full 1.5e9-point C3 field under each (patch, ghost) the autotuner weighs
+    (16/8 is the case above): all points against the separable reference."""
+    _large_case("C3", 3, 2, 31, patch=M, ghost=g)
 
 
 def test_c4_one_gpu_share_50_steps():

@@ -161,3 +161,17 @@ def test_generator_cubes_match_full_field():
     cubes = inputs.gaussian_cubes(grid, pk, kidx)
     for n, (i1, i2, i3) in enumerate(kidx):
         assert np.allclose(cubes[n], full[i3, i2, i1], rtol=1e-14, atol=1e-300)
+
+
+def test_compiled_shapes_cover_every_tuned_configuration():
+    """The kernels the workloads and the autotuner need are compiled (the registry is
+    enumerated through descriptor validation alone)."""
+    s = set(chasm.compiled_shapes())
+    need = {("f64", 16, 8, 4, "pmbc"), ("f64", 16, 8, 4, "poly3"), ("f32", 32, 8, 6, "pmbc"),
+            ("f64", 32, 8, 6, "pmbc")}
+    need |= {("f32", 48, m, g, "pmbc") for m in (8, 12, 16) for g in (4, 6, 8)}
+    need |= {("f32", 64, m, g, "pmbc") for m in (8, 16) for g in (4, 6, 8)}
+    need |= {("f32", n, 8, 6, "pmbc") for n in (16, 24, 32, 48)}     # serving shapes
+    assert need <= s, need - s
+    for dt, n, m, g, cl in s:
+        assert n % m == 0 and 1 <= g < n

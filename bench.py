@@ -211,6 +211,74 @@ def bench_serving(args):
     }
 
 
+THETA_FLOP_NOTE = ("conventional count of one period-2N_k FFT convolution per x-point and nucleus: "
+                   "2 x 5 P^3 log2(P^3) + 2 P^3 flops, P = 2 N_k")
+
+
+def theta_flops_per_xpoint(nk: int) -> float:
+    P3 = (2 * nk) ** 3
+    return 2 * 5 * P3 * np.log2(P3) + 2 * P3
+
+
+def bench_theta(args):
+    """Theta_V^T (Sec. 4) on the paper's N_k = 16 grid of Sec. 5.2: 61^3 x-nodes on
+    [-9, 9]^3 by 16^3 k-nodes on [-6.4, 6.4)^3, one nucleus at the origin, FP32 field,
+    FP64 arithmetic."""
+    import torch
+    from paper_2205_02380_amd import inputs, theta
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    grid = inputs.Grid((61,) * 3, (-9.0,) * 3, (9.3,) * 3, (16,) * 3, (-6.4,) * 3, (6.4,) * 3)
+    pk = inputs.random_packets(4, 21, c_range=(-3.0, 3.0), k0_range=(-1.0, 1.0), s_range=(0.8, 1.5))
+    f = torch.empty(grid.shape(), dtype=torch.float32, device=dev)
+    coef, gx, gk = inputs.packet_factors(grid, pk)
+    inputs.fill_separable(f, coef, gx, gk)
+    out = torch.empty_like(f)
+    th = theta.Theta(grid, [(0.0, 0.0, 0.0)], dtype="f32", stream=stream)
+    for _ in range(args.warmup):
+        th.apply(f, out)
+    torch.cuda.synchronize()
+    steps = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        th.apply(f, out)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    total_s = ev[0].elapsed_time(ev[steps]) / 1e3
+    npts = grid.cube
+    flops = theta_flops_per_xpoint(16) * npts
+    mean_s = float(per.mean()) / 1e3
+    cpu = None
+    if not args.no_cpu:
+        from oracle import tkm
+        rng = np.random.default_rng(23)
+        xidx = np.stack([rng.integers(0, 61, 16) for _ in range(3)], axis=1)
+        fx = [f[:, :, :, i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in xidx]
+        t0 = time.perf_counter()
+        for n, (i1, i2, i3) in enumerate(xidx):
+            tkm.theta_point(fx[n], (grid.x_axis(0)[i1], grid.x_axis(1)[i2], grid.x_axis(2)[i3]), grid.k_lo, grid.hk)
+        tc = time.perf_counter() - t0
+        cpu = {"value": len(xidx) * grid.nkpts / tc, "unit": "point-evaluations/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(xidx)} seeded x-points x 4096 k-points ({tc:.1f} s, numpy FP64, threefold transforms)"}
+    th.close()
+    return {
+        "metric": "Theta_V^T point-evaluations/s (truncated kernel method, FP64 arithmetic)",
+        "value": grid.points * steps / total_s, "unit": "point-evaluations/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": total_s * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 (f32 field)", "data": "synthetic (seeded Gaussian-packet mixture)",
+        "config": {"workload": "theta: 61^3 x [-9,9]^3 by 16^3 k [-6.4,6.4)^3, 929,714,176 points, one nucleus, "
+                               "FP32 field, FP64 transforms"},
+        "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
+                            "mean": float(per.mean())},
+        "roofline": {"bound": "alu", "achieved": flops / mean_s / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": flops / mean_s / 1e12 / 78.6, "traffic": None,
+                     "kernel": "whole apply (transpose, k_theta, transpose)", "flop_count": THETA_FLOP_NOTE},
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,7 +288,7 @@ def main():
     ap.add_argument("--cpu-kpoints", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "serving"])
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "serving", "theta"])
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -252,6 +320,9 @@ def main():
         return
     if args.workload == "serving":
         print(json.dumps(bench_serving(args)), flush=True)
+        return
+    if args.workload == "theta":
+        print(json.dumps(bench_theta(args)), flush=True)
         return
     w = inputs.workload("C2")
     g = w.grid

@@ -144,6 +144,12 @@ struct chasm_advect_s {
 
 static thread_local std::string g_err;
 
+namespace chasm {
+// The other C entry points of the library (chasm_theta.h) report through the same
+// thread-local message.
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace chasm
+
 static chasm_status fail(chasm_status st, const std::string& msg)
 {
     g_err = msg;

@@ -1,0 +1,66 @@
+"""CPU tests of the Theta_V library side (``include/chasm_theta.h``): descriptor layout
+and validation without a device, and the library's FP64 tensor of eq. 4.9 (its own
+sine integral, its own separable inverse transform) against the oracle's."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from oracle import tkm
+from paper_2205_02380_amd import chasm, inputs, theta
+
+
+def grid(nx=4, nk=8, L=6.4):
+    return inputs.Grid((nx,) * 3, (-9.0,) * 3, (9.0,) * 3, (nk,) * 3, (-L,) * 3, (L,) * 3)
+
+
+def test_desc_layout():
+    d = theta.chasm_theta_desc()
+    assert ctypes.sizeof(d) == 264
+    assert theta.chasm_theta_desc.x_nuc.offset == 128
+    assert theta.chasm_theta_desc.dtype.offset == 256
+
+
+@pytest.mark.parametrize("nk,lo,hi", [((8, 8, 8), (-2.0,) * 3, (2.0,) * 3),
+                                      ((16, 16, 16), (-6.4,) * 3, (6.4,) * 3),
+                                      ((6, 8, 4), (-1.2, -3.0, -1.4), (1.2, 2.0, 2.6))])
+def test_library_tensor_matches_oracle(nk, lo, hi):
+    g = inputs.Grid((2, 2, 2), (0.0,) * 3, (1.0,) * 3, nk, lo, hi)
+    got = theta.chasm_theta_tensor(theta.make_desc(g, [(0.0, 0.0, 0.0)]))
+    ref = tkm.tkm_tensor(nk, g.hk)
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda d: d.nk.__setitem__(0, 7), chasm.CHASM_EINVAL),
+    (lambda d: [d.nk.__setitem__(a, 12) for a in range(3)], chasm.CHASM_EUNSUPPORTED),
+    (lambda d: d.nk.__setitem__(2, 16), chasm.CHASM_EUNSUPPORTED),
+    (lambda d: setattr(d, "nnuc", 0), chasm.CHASM_EINVAL),
+    (lambda d: setattr(d, "nnuc", 5), chasm.CHASM_EINVAL),
+    (lambda d: setattr(d, "dtype", 7), chasm.CHASM_EINVAL),
+    (lambda d: setattr(d, "nbatch", 0), chasm.CHASM_EINVAL),
+    (lambda d: d.z_nuc.__setitem__(0, float("nan")), chasm.CHASM_EINVAL),
+    (lambda d: d.k_hi.__setitem__(1, d.k_lo[1]), chasm.CHASM_EINVAL),
+    (lambda d: d.nx.__setitem__(0, 0), chasm.CHASM_EINVAL),
+])
+def test_descriptor_validation(mutate, status):
+    d = theta.make_desc(grid(), [(0.0, 0.0, 0.0)])
+    mutate(d)
+    with pytest.raises(chasm.ChasmError) as ei:
+        theta.chasm_theta_workspace_bytes(d)
+    assert ei.value.status == status
+
+
+def test_workspace_and_null_arguments():
+    d = theta.make_desc(grid(nx=61, nk=16), [(0.0, 0.0, 0.0)])
+    b = theta.chasm_theta_workspace_bytes(d)
+    assert b >= 61 ** 3 * 16 ** 3 * 4 + 32 ** 3 * 8
+    L = theta.lib()
+    assert L.chasm_theta_create(None, None, None) == chasm.CHASM_EINVAL
+    assert L.chasm_theta_apply(None, None, None) == chasm.CHASM_EINVAL
+    assert L.chasm_theta_destroy(None) == chasm.CHASM_OK
+    h = ctypes.c_void_p()
+    assert L.chasm_theta_create(ctypes.byref(d), None, None) == chasm.CHASM_EINVAL
+    assert h.value is None

@@ -102,22 +102,23 @@ struct ThetaShape {
     static_assert(C <= NK ? NK % C == 0 : C == 2 * NK, "chunk length");
 };
 
-template <typename T, int NK, int R, int NT>
-__global__ __launch_bounds__(NT) void k_theta(T* __restrict__ fx, const double* __restrict__ that, const ThetaArgs a,
+template <typename T, int NK, int R, int NT, int WPE = 1>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_theta(T* __restrict__ fx, const double* __restrict__ that, const ThetaArgs a,
                                              long long total)
 {
     using namespace fft;
     using S = ThetaShape<NK, R>;
     constexpr int P = S::P, C = S::C, RS = S::RS;
     constexpr int LA = NK * NK, LB = C * NK, LC = C * P;
-    static_assert(LA <= NT, "one k1 line per thread");
+    // k1 lines owned by a thread in stages A and E (the only state kept across chunks
+    // is the real result of each owned line; the input line is re-read from memory)
+    constexpr int LPT = LA >= NT ? LA / NT : 1;
+    static_assert(LA < NT || LA % NT == 0, "whole k1 lines per thread");
     __shared__ cd W1[S::W1N];
     __shared__ cd W2[S::W2N];
     __shared__ cd E[3][NK];
 
     const int tid = threadIdx.x;
-    const bool has_line = tid < LA;
-    const int k2 = tid % NK, k3 = tid / NK;
 
     for (long long xp = blockIdx.x; xp < total; xp += gridDim.x) {
         const long long loc = xp % a.npts;
@@ -125,15 +126,15 @@ __global__ __launch_bounds__(NT) void k_theta(T* __restrict__ fx, const double* 
         const int i2 = (int)((loc / a.nx[0]) % a.nx[1]);
         const int i3 = (int)(loc / ((long long)a.nx[0] * a.nx[1]));
         const double xc[3] = {a.x_lo[0] + i1 * a.hx[0], a.x_lo[1] + i2 * a.hx[1], a.x_lo[2] + i3 * a.hx[2]};
+        T* base = fx + xp * (long long)(NK * NK * NK);
 
-        T* line = fx + xp * (long long)(NK * NK * NK) + (long long)(has_line ? tid : 0) * NK;
-        double fv[NK];
-        double th[NK];
-        if (has_line) load_k1<T, NK>(line, fv);
-        for (int j = 0; j < NK; ++j) th[j] = 0.0;
+        double th[LPT][NK];
+        sfor<0, LPT>([&](auto lc) {
+            sfor<0, NK>([&](auto jc) { th[decltype(lc)::value][decltype(jc)::value] = 0.0; });
+        });
 
         for (int nu = 0; nu < a.nnuc; ++nu) {
-            __syncthreads();   // E and W1 of the previous pass are free
+            __syncthreads();   // E of the previous pass is no longer read
             if (tid < 3 * NK) {
                 const int d = tid / NK, k = tid % NK;
                 const double ph = 2.0 * (xc[d] - a.xa[nu][d]) * a.hk[d] * k;
@@ -142,46 +143,49 @@ __global__ __launch_bounds__(NT) void k_theta(T* __restrict__ fx, const double* 
                 E[d][k] = cd{c, -s};                                  // e^{-i phi_d k}
             }
             __syncthreads();
-            cd z[NK], acc[NK];
-            cd e23{1.0, 0.0};
-            if (has_line) {
-                e23 = cmul(E[1][k2], E[2][k3]);
-                sfor<0, NK>([&](auto jc) {
-                    constexpr int j = decltype(jc)::value;
-                    const cd e = cmul(E[0][j], e23);
-                    z[j] = cd{e.re * fv[j], e.im * fv[j]};
-                    acc[j] = cd{0.0, 0.0};
-                });
-            }
+            const double w = a.wgt[nu];
             sfor<0, R>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
-                // ---- A: k1 forward of this chunk (xi1 = r + R m)
-                if (has_line) {
-                    cd Y[C];
-                    if constexpr (C <= NK) {
-                        sfor<0, C>([&](auto jc) {
-                            constexpr int j = decltype(jc)::value;
-                            cd s{0.0, 0.0};
-                            sfor<0, NK / C>([&](auto sc) {
-                                constexpr int k = j + decltype(sc)::value * C;
-                                s = cadd(s, tmul<(long long)r * k, P, -1>(z[k]));
-                            });
-                            Y[j] = s;
-                        });
-                        transform<C, -1>(Y);
-                    } else {
-                        cd y[NK];
+                // ---- A: k1 forward of this chunk (xi1 = r + R m) from the modulated line
+                sfor<0, LPT>([&](auto lc) {
+                    const int la = tid + decltype(lc)::value * NT;
+                    if (la < LA) {
+                        const int k2 = la % NK, k3 = la / NK;
+                        double fv[NK];
+                        load_k1<T, NK>(base + (long long)la * NK, fv);
+                        const cd e23 = cmul(E[1][k2], E[2][k3]);
+                        cd z[NK];
                         sfor<0, NK>([&](auto jc) {
                             constexpr int j = decltype(jc)::value;
-                            y[j] = tmul<(long long)r * j, P, -1>(z[j]);
+                            const cd e = cmul(E[0][j], e23);
+                            z[j] = cd{e.re * fv[j], e.im * fv[j]};
                         });
-                        fft_fwd_padded<NK>(y, Y);
+                        cd Y[C];
+                        if constexpr (C <= NK) {
+                            sfor<0, C>([&](auto jc) {
+                                constexpr int j = decltype(jc)::value;
+                                cd s{0.0, 0.0};
+                                sfor<0, NK / C>([&](auto sc) {
+                                    constexpr int k = j + decltype(sc)::value * C;
+                                    s = cadd(s, tmul<(long long)r * k, P, -1>(z[k]));
+                                });
+                                Y[j] = s;
+                            });
+                            transform<C, -1>(Y);
+                        } else {
+                            cd y[NK];
+                            sfor<0, NK>([&](auto jc) {
+                                constexpr int j = decltype(jc)::value;
+                                y[j] = tmul<(long long)r * j, P, -1>(z[j]);
+                            });
+                            fft_fwd_padded<NK>(y, Y);
+                        }
+                        sfor<0, C>([&](auto mc) {
+                            constexpr int m = decltype(mc)::value;
+                            W1[(m * NK + k3) * RS + k2] = Y[m];
+                        });
                     }
-                    sfor<0, C>([&](auto mc) {
-                        constexpr int m = decltype(mc)::value;
-                        W1[(m * NK + k3) * RS + k2] = Y[m];
-                    });
-                }
+                });
                 __syncthreads();
                 // ---- B: k2 forward, zero-padded to P
                 for (int ln = tid; ln < LB; ln += NT) {
@@ -236,42 +240,43 @@ __global__ __launch_bounds__(NT) void k_theta(T* __restrict__ fx, const double* 
                     });
                 }
                 __syncthreads();
-                // ---- E: k1 inverse of this chunk into the accumulator
-                if (has_line) {
-                    cd v[C];
-                    sfor<0, C>([&](auto mc) {
-                        constexpr int m = decltype(mc)::value;
-                        v[m] = W1[(m * NK + k3) * RS + k2];
-                    });
-                    if constexpr (C <= NK) {
-                        transform<C, +1>(v);
-                        sfor<0, NK>([&](auto kc) {
-                            constexpr int k = decltype(kc)::value;
-                            acc[k] = cadd(acc[k], tmul<(long long)r * k, P, +1>(v[k % C]));
+                // ---- E: k1 inverse of this chunk, demodulated, into the real result
+                sfor<0, LPT>([&](auto lc) {
+                    constexpr int l = decltype(lc)::value;
+                    const int la = tid + l * NT;
+                    if (la < LA) {
+                        const int k2 = la % NK, k3 = la / NK;
+                        const cd e23c = conj(cmul(E[1][k2], E[2][k3]));
+                        cd v[C];
+                        sfor<0, C>([&](auto mc) {
+                            constexpr int m = decltype(mc)::value;
+                            v[m] = W1[(m * NK + k3) * RS + k2];
                         });
-                    } else {
-                        cd vh[NK];
-                        fft_inv_half<NK>(v, vh);
-                        sfor<0, NK>([&](auto kc) {
+                        auto put = [&](auto kc, cd x) {
                             constexpr int k = decltype(kc)::value;
-                            acc[k] = cadd(acc[k], tmul<(long long)r * k, P, +1>(vh[k]));
-                        });
+                            const cd d = cmul(conj(E[0][k]), e23c);             // e^{+i phi.p}
+                            const cd t = cmul(d, tmul<(long long)r * k, P, +1>(x));
+                            th[l][k] += w * t.im;
+                        };
+                        if constexpr (C <= NK) {
+                            transform<C, +1>(v);
+                            sfor<0, NK>([&](auto kc) { put(kc, v[decltype(kc)::value % C]); });
+                        } else {
+                            cd vh[NK];
+                            fft_inv_half<NK>(v, vh);
+                            sfor<0, NK>([&](auto kc) { put(kc, vh[decltype(kc)::value]); });
+                        }
                     }
-                }
+                });
                 __syncthreads();
             });
-            if (has_line) {
-                const double w = a.wgt[nu];
-                const cd e23c = conj(e23);
-                sfor<0, NK>([&](auto jc) {
-                    constexpr int j = decltype(jc)::value;
-                    const cd d = cmul(conj(E[0][j]), e23c);             // e^{+i phi.p}
-                    const cd t = cmul(d, acc[j]);
-                    th[j] += w * t.im;
-                });
-            }
         }
-        if (has_line) store_k1<T, NK>(line, th);
+        __syncthreads();   // every line of this x-point is read (stage A) before any is written
+        sfor<0, LPT>([&](auto lc) {
+            constexpr int l = decltype(lc)::value;
+            const int la = tid + l * NT;
+            if (la < LA) store_k1<T, NK>(base + (long long)la * NK, th[l]);
+        });
     }
 }
 

@@ -121,6 +121,17 @@ chasm_status chasm_advect_mass(chasm_advect_t h, double* mass, double* l2, doubl
  * Synchronises the handle's stream. */
 chasm_status chasm_advect_diagnostics(chasm_advect_t h, double* out);
 
+/* The visualisation observables of Sec. 5 for each batch member b, in FP64 (host
+ * arrays; any may be NULL to skip it):
+ *   w1[b][k1][x1] = W_1(x1, k1) = integral of f over x2, x3, k2, k3  (nbatch*nk[0]*nx[0])
+ *   w2[b][k2][x2], w3[b][k3][x3] likewise                              (nbatch*nk[d]*nx[d])
+ *   p12[b][x2][x1] = P(x1, x2) = integral of f over x3 and k           (nbatch*nx[1]*nx[0])
+ * Integrals are cell sums times the spacings of the integrated variables (the
+ * paper's "average over the grid" convention, as for the mass).  The field is read
+ * once; the first call allocates nbatch*nk1*nk2*nk3*(3N + N^2) doubles of device
+ * workspace, kept until destroy.  Synchronises the handle's stream. */
+chasm_status chasm_advect_marginals(chasm_advect_t h, double* w1, double* w2, double* w3, double* p12);
+
 /* Diagnostics recorded by CHASM_FLAG_REDUCE_EACH_STEP, oldest first:
  * out[s*nbatch*8 + b*8 + i] for s < *n_out (at most max_steps, host memory).
  * Synchronises the handle's stream. */

@@ -62,7 +62,7 @@ class chasm_advect_desc(ctypes.Structure):
 EXPORTS = (
     "chasm_advect_create", "chasm_advect_step", "chasm_advect_mass", "chasm_advect_diagnostics",
     "chasm_advect_history", "chasm_advect_step_many", "chasm_advect_workspace_bytes", "chasm_advect_schedule",
-    "chasm_advect_destroy", "chasm_advect_last_error", "chasm_advect_version",
+    "chasm_advect_destroy", "chasm_advect_last_error", "chasm_advect_version", "chasm_advect_marginals",
 )
 
 _lib = None
@@ -87,10 +87,11 @@ def lib():
     L.chasm_advect_workspace_bytes.argtypes = [pdesc, ctypes.POINTER(ctypes.c_size_t)]
     L.chasm_advect_schedule.argtypes = [vp, ctypes.POINTER(i32)]
     L.chasm_advect_destroy.argtypes = [vp]
+    L.chasm_advect_marginals.argtypes = [vp, pd, pd, pd, pd]
     L.chasm_advect_last_error.restype = ctypes.c_char_p
     L.chasm_advect_version.restype = ctypes.c_char_p
     for name in ("create", "step", "mass", "diagnostics", "history", "step_many", "workspace_bytes", "schedule",
-                 "destroy"):
+                 "destroy", "marginals"):
         getattr(L, "chasm_advect_" + name).restype = ctypes.c_int
     _lib = L
     return L
@@ -163,6 +164,15 @@ def chasm_advect_step_many(hs: Sequence[int], nsteps: Sequence[int]) -> None:
     _check(lib().chasm_advect_step_many(arr, n, st))
 
 
+def chasm_advect_marginals(h: int, grid: Grid, nbatch: int):
+    """(W1, W2, W3, P): arrays [b][k_d][x_d] for W_d and [b][x2][x1] for P (FP64)."""
+    ws = [np.zeros((nbatch, grid.nk[d], grid.nx[d])) for d in range(3)]
+    p = np.zeros((nbatch, grid.nx[1], grid.nx[0]))
+    ptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().chasm_advect_marginals(ctypes.c_void_p(h), ptr(ws[0]), ptr(ws[1]), ptr(ws[2]), ptr(p)))
+    return ws[0], ws[1], ws[2], p
+
+
 def chasm_advect_workspace_bytes(desc: chasm_advect_desc) -> int:
     b = ctypes.c_size_t()
     _check(lib().chasm_advect_workspace_bytes(ctypes.byref(desc), ctypes.byref(b)))
@@ -221,6 +231,11 @@ class Advect:
 
     def diagnostics(self) -> np.ndarray:
         return chasm_advect_diagnostics(self.h, self.nbatch)
+
+    def marginals(self):
+        """Reduced Wigner functions W1, W2, W3 ([b][k_d][x_d]) and the spatial marginal
+        P ([b][x2][x1]) of the current field (Sec. 5), FP64."""
+        return chasm_advect_marginals(self.h, self.grid, self.nbatch)
 
     def history(self, max_steps: int = 1 << 20) -> np.ndarray:
         return chasm_advect_history(self.h, self.nbatch, max_steps)

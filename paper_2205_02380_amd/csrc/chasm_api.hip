@@ -131,6 +131,8 @@ struct chasm_advect_s {
     void* tables = nullptr;          // device block: FP64 tables then FP32 mirror, int shifts
     double* partials = nullptr;      // [rows][NRED]
     double* fold = nullptr;          // [nbatch][FOLD_CHUNKS][NRED]
+    double* marg_part = nullptr;     // item rows of the marginals (allocated on first use)
+    double* marg_out = nullptr;
     long long partial_rows = 0;      // rows per batch member when reducing each step
     double* last = nullptr;          // [nbatch][NRED]
     double* hist = nullptr;          // [cap][nbatch][NRED]
@@ -145,6 +147,10 @@ struct chasm_advect_s {
 static thread_local std::string g_err;
 
 namespace chasm {
+long long marginal_row(int N);
+hipError_t launch_marginals(int dtype, int N, const int nk[3], int nbatch, const double hx[3], const double hk[3],
+                            const void* f, double* part, double* out, hipStream_t st);
+
 // The other C entry points of the library (chasm_theta.h) report through the same
 // thread-local message.
 void set_last_error(const std::string& msg) { g_err = msg; }
@@ -508,6 +514,42 @@ chasm_status chasm_advect_diagnostics(chasm_advect_t h, double* out)
     return CHASM_OK;
 }
 
+chasm_status chasm_advect_marginals(chasm_advect_t h, double* w1, double* w2, double* w3, double* p12)
+{
+    if (!h) return fail(CHASM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
+    const chasm_advect_desc& d = h->desc;
+    const int N = d.nx[0];
+    const long long nitems = (long long)d.nk[0] * d.nk[1] * d.nk[2] * d.nbatch;
+    const long long per_b = (long long)N * (d.nk[0] + d.nk[1] + d.nk[2]) + (long long)N * N;
+    if (!h->marg_part) {
+        if (hipMalloc((void**)&h->marg_part, (size_t)nitems * marginal_row(N) * sizeof(double)) != hipSuccess)
+            return fail(CHASM_ENOMEM, "hipMalloc(marginal rows) failed");
+        if (hipMalloc((void**)&h->marg_out, (size_t)per_b * d.nbatch * sizeof(double)) != hipSuccess)
+            return fail(CHASM_ENOMEM, "hipMalloc(marginals) failed");
+    }
+    double hx[3], hk[3];
+    for (int a = 0; a < 3; ++a) {
+        hx[a] = (d.x_hi[a] - d.x_lo[a]) / d.nx[a];
+        hk[a] = (d.k_hi[a] - d.k_lo[a]) / d.nk[a];
+    }
+    hipError_t e = launch_marginals(d.dtype, N, d.nk, d.nbatch, hx, hk, h->f, h->marg_part, h->marg_out, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "marginals launch");
+    std::vector<double> all((size_t)per_b * d.nbatch);
+    e = hipMemcpyAsync(all.data(), h->marg_out, all.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "marginals copy");
+    const size_t n1 = (size_t)N * d.nk[0], n2 = (size_t)N * d.nk[1], n3 = (size_t)N * d.nk[2], np = (size_t)N * N;
+    for (int b = 0; b < d.nbatch; ++b) {
+        const double* src = all.data() + (size_t)b * per_b;
+        if (w1) std::memcpy(w1 + b * n1, src, n1 * sizeof(double));
+        if (w2) std::memcpy(w2 + b * n2, src + n1, n2 * sizeof(double));
+        if (w3) std::memcpy(w3 + b * n3, src + n1 + n2, n3 * sizeof(double));
+        if (p12) std::memcpy(p12 + b * np, src + n1 + n2 + n3, np * sizeof(double));
+    }
+    return CHASM_OK;
+}
+
 chasm_status chasm_advect_mass(chasm_advect_t h, double* mass, double* l2, double* moments6)
 {
     if (!h || !mass) return fail(CHASM_EINVAL, "NULL argument");
@@ -567,6 +609,8 @@ chasm_status chasm_advect_destroy(chasm_advect_t h)
     if (h->tables) hipFree(h->tables);
     if (h->partials) hipFree(h->partials);
     if (h->fold) hipFree(h->fold);
+    if (h->marg_part) hipFree(h->marg_part);
+    if (h->marg_out) hipFree(h->marg_out);
     if (h->last) hipFree(h->last);
     if (h->hist) hipFree(h->hist);
     if (h->counter) hipFree(h->counter);

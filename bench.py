@@ -279,6 +279,61 @@ def bench_theta(args):
     }
 
 
+def bench_lpc1(args):
+    """Full LPC1 steps of the Wigner-Coulomb equation (Sec. 2.2): the characteristic step
+    and two truncated-kernel Theta_V evaluations per step.  Hydrogen (one proton at the
+    origin) on 64^3 x-nodes on [-9.6, 9.6)^3 (dx = 0.3, the paper's spacing) by 16^3
+    k-nodes on [-6.4, 6.4)^3 (dk = 0.8), patch 16, ghost 8, tau = 0.025, FP32 field."""
+    import torch
+    from paper_2205_02380_amd import inputs, lpc1
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    grid = inputs.Grid((64,) * 3, (-9.6,) * 3, (9.6,) * 3, (16,) * 3, (-6.4,) * 3, (6.4,) * 3)
+    pk = inputs.random_packets(4, 31, c_range=(-3.0, 3.0), k0_range=(-1.0, 1.0), s_range=(0.8, 1.5))
+    f = torch.empty(grid.shape(), dtype=torch.float32, device=dev)
+    coef, gx, gk = inputs.packet_factors(grid, pk)
+    inputs.fill_separable(f, coef, gx, gk)
+    tau = 0.025
+    s = lpc1.LPC1(f, grid, 16, 8, tau, [(0.0, 0.0, 0.0)], stream=stream)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    steps = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        s.step(1)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    s.close()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    total_s = ev[0].elapsed_time(ev[steps]) / 1e3
+    flops = 2 * theta_flops_per_xpoint(16) * grid.cube
+    cpu = None
+    if not args.no_cpu:
+        from oracle import lpc1 as olpc1
+        small = inputs.Grid((8,) * 3, (-1.2,) * 3, (1.2,) * 3, (16,) * 3, (-6.4,) * 3, (6.4,) * 3)
+        f0 = inputs.gaussian_field(small, pk).numpy()
+        t0 = time.perf_counter()
+        olpc1.lpc1(f0, small, 4, 3, tau, 1, [(0.0, 0.0, 0.0)], [1.0], direct=False)
+        tc = time.perf_counter() - t0
+        cpu = {"value": small.points / tc, "unit": "point-updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"one LPC1 step of an 8^3 x 16^3 grid ({small.points} points, {tc:.1f} s; numpy/C FP64)"}
+    return {
+        "metric": "LPC1 point-updates/s (Wigner-Coulomb step: advection + 2 truncated-kernel Theta_V)",
+        "value": grid.points * steps / total_s, "unit": "point-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": total_s * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 field, f64 Theta", "data": "synthetic (seeded Gaussian-packet mixture)",
+        "config": {"workload": "lpc1: 64^3 x [-9.6,9.6)^3 by 16^3 k [-6.4,6.4)^3, 1,073,741,824 points, one proton, "
+                               "patch 16, ghost 8, tau 0.025"},
+        "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
+                            "mean": float(per.mean())},
+        "roofline": {"bound": "alu", "achieved": flops / (float(per.mean()) / 1e3) / 1e12, "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": flops / (float(per.mean()) / 1e3) / 1e12 / 78.6, "traffic": None,
+                     "kernel": "whole step (two Theta evaluations dominate)", "flop_count": THETA_FLOP_NOTE},
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,7 +343,7 @@ def main():
     ap.add_argument("--cpu-kpoints", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "serving", "theta"])
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "serving", "theta", "lpc1"])
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -323,6 +378,9 @@ def main():
         return
     if args.workload == "theta":
         print(json.dumps(bench_theta(args)), flush=True)
+        return
+    if args.workload == "lpc1":
+        print(json.dumps(bench_lpc1(args)), flush=True)
         return
     w = inputs.workload("C2")
     g = w.grid

@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "libchasm_oracle.so")
 
 PMBC = 0    # paper closure: truncated rows of the natural-BC inverse (eqs. 3.4-3.5)
 POLY3 = 1   # cubic-exact variant of those rows (not in the paper; see module docstring of the C file)
+NEUMANN = 2  # rows of the inverse of the zero-slope Hermite (Neumann) global matrix (eq. 2.13)
 
 _lib = None
 
@@ -52,6 +53,8 @@ def _load():
     lib.chasm_oracle_line_coefficients.argtypes = [i, i, d, i, pd, pd, pd]
     lib.chasm_oracle_line.argtypes = [i, i, d, i, pd, d, pd, pd]
     lib.chasm_oracle_global_line.argtypes = [i, d, d, pd, pd]
+    lib.chasm_oracle_global_line_bc.argtypes = [i, d, i, d, pd, pd]
+    lib.chasm_oracle_global_inverse.argtypes = [i, d, i, pd]
     lib.chasm_oracle_advect6d.argtypes = [pi, pd, pi, pd, pd, pi, i, i, d, i, i, pi, pd, i]
     lib.chasm_oracle_reduce.argtypes = [pi, pd, pd, pi, pd, pd, i, pd, pd]
     _lib = lib
@@ -133,11 +136,21 @@ def line(N: int, M: int, g: int, h: float, alpha: float, phi, closure: int = PMB
     return out
 
 
-def global_line(N: int, h: float, alpha: float, phi) -> np.ndarray:
-    """Brute-force reference: global natural spline (eq. 2.15 with eq. 2.14), no patches."""
+def global_line(N: int, h: float, alpha: float, phi, bc: int = 0) -> np.ndarray:
+    """Brute-force reference: the global spline of the whole line, no patches, with the
+    natural boundary rows (bc 0, eq. 2.14) or the zero-slope Hermite rows (bc 1, the
+    Neumann condition of eq. 2.13 with phi_L = phi_R = 0)."""
     phi = _f64(phi)
     out = np.zeros(N)
-    _check(_load().chasm_oracle_global_line(N, float(h), float(alpha), _dp(phi), _dp(out)), "global_line")
+    _check(_load().chasm_oracle_global_line_bc(N, float(h), int(bc), float(alpha), _dp(phi), _dp(out)),
+           "global_line")
+    return out
+
+
+def global_inverse(N: int, h: float, bc: int) -> np.ndarray:
+    """Inverse of the global spline matrix with natural (bc 0) or Neumann (bc 1) rows."""
+    out = np.zeros((N + 2, N + 2))
+    _check(_load().chasm_oracle_global_inverse(N, float(h), int(bc), _dp(out)), "global_inverse")
     return out
 
 

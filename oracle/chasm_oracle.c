@@ -31,6 +31,9 @@
  *   - the patch whose cells contain the departure point evaluates it (the upwind
  *     patch of the correction procedure, Sec. 3.1.3);
  *   - shifts of any size: the departure cell is floor(j - alpha);
+ *   - optional closure NEUMANN: the global matrix takes the Hermite boundary rows of
+ *     eq. 2.13 with zero end slopes (the Neumann condition the paper names as the
+ *     alternative to the natural one); stencils are rows of its inverse;
  *   - optional closure POLY3 (not in the paper): the truncated stencil rows get the
  *     minimum-norm correction that makes them exact for cubic data, and the outer
  *     ghost coefficient is extrapolated by a zero fourth difference, so cubic
@@ -45,6 +48,7 @@
 
 #define ORACLE_CLOSURE_PMBC 0
 #define ORACLE_CLOSURE_POLY3 1
+#define ORACLE_CLOSURE_NEUMANN 2
 
 /* ------------------------------------------------------------------------- */
 /* Cubic B-spline centred at 0, support [-2, 2]: eq. (2.10) with x = x_nu + t*h. */
@@ -150,21 +154,41 @@ static int gj_inverse(int n, double *a, double *inv)
  *   1..N   : interpolation at node i = row-1 (eq. 2.12)
  *   N+1    : s''(x_{N-1}) = 0  (eq. 2.14)
  * inv is (N+2) x (N+2) row-major.  Returns 0 on success. */
+int chasm_oracle_global_inverse(int N, double h, int bc, double *inv);
+
 int chasm_oracle_natural_inverse(int N, double h, double *inv)
 {
-    if (N < 2 || !(h > 0.0)) return -1;
+    return chasm_oracle_global_inverse(N, h, 0, inv);
+}
+
+/* The global spline matrix with either boundary rows: bc 0 natural (eq. 2.14),
+ * bc 1 Neumann, i.e. the Hermite rows of eq. 2.13 with phi_L = phi_R = 0:
+ *   row 0   : (eta_1 - eta_{-1}) / 2h = 0
+ *   row N+1 : (eta_N - eta_{N-2}) / 2h = 0
+ * (the right-hand sides of the boundary rows are 0, so only data columns matter). */
+int chasm_oracle_global_inverse(int N, double h, int bc, double *inv)
+{
+    if (N < 2 || !(h > 0.0) || (bc != 0 && bc != 1)) return -1;
     int n = N + 2;
     double *a = (double *)calloc((size_t)n * n, sizeof(double));
     if (!a) return -2;
-    double ih2 = 1.0 / (h * h);
-    a[0 * n + 0] = ih2; a[0 * n + 1] = -2.0 * ih2; a[0 * n + 2] = ih2;
+    double ih2 = 1.0 / (h * h), i2h = 1.0 / (2.0 * h);
+    if (bc == 0) {
+        a[0 * n + 0] = ih2; a[0 * n + 1] = -2.0 * ih2; a[0 * n + 2] = ih2;
+    } else {
+        a[0 * n + 0] = -i2h; a[0 * n + 2] = i2h;
+    }
     for (int i = 0; i < N; ++i) {
         int r = i + 1;
         a[r * n + i] += 1.0 / 6.0;        /* eta_{i-1} */
         a[r * n + i + 1] += 2.0 / 3.0;    /* eta_i     */
         a[r * n + i + 2] += 1.0 / 6.0;    /* eta_{i+1} */
     }
-    a[(N + 1) * n + (N - 1)] = ih2; a[(N + 1) * n + N] = -2.0 * ih2; a[(N + 1) * n + (N + 1)] = ih2;
+    if (bc == 0) {
+        a[(N + 1) * n + (N - 1)] = ih2; a[(N + 1) * n + N] = -2.0 * ih2; a[(N + 1) * n + (N + 1)] = ih2;
+    } else {
+        a[(N + 1) * n + (N - 1)] = -i2h; a[(N + 1) * n + (N + 1)] = i2h;
+    }
     int rc = gj_inverse(n, a, inv);
     free(a);
     return rc;
@@ -181,11 +205,12 @@ int chasm_oracle_stencils(int N, int M, int g, double h, int closure, double *c)
 {
     int p = chasm_oracle_npatch(N, M);
     if (p < 1 || g < 1 || !(h > 0.0)) return -1;
-    if (closure != ORACLE_CLOSURE_PMBC && closure != ORACLE_CLOSURE_POLY3) return -1;
+    if (closure != ORACLE_CLOSURE_PMBC && closure != ORACLE_CLOSURE_POLY3 && closure != ORACLE_CLOSURE_NEUMANN)
+        return -1;
     int n = N + 2;
     double *inv = (double *)malloc((size_t)n * n * sizeof(double));
     if (!inv) return -2;
-    int rc = chasm_oracle_natural_inverse(N, h, inv);
+    int rc = chasm_oracle_global_inverse(N, h, closure == ORACLE_CLOSURE_NEUMANN ? 1 : 0, inv);
     if (rc) { free(inv); return rc; }
     memset(c, 0, (size_t)(p + 1) * N * sizeof(double));
     for (int q = 0; q <= p; ++q) {
@@ -339,13 +364,22 @@ int chasm_oracle_line(int N, int M, double h, int closure, const double *c, doub
 
 /* Brute-force global reference: the natural spline of the whole line (eq. 2.15 with
  * eq. 2.14), no patches, ghosts eta_{-2} = eta_{N+1} = 0. */
+int chasm_oracle_global_line_bc(int N, double h, int bc, double alpha, const double *phi, double *out);
+
 int chasm_oracle_global_line(int N, double h, double alpha, const double *phi, double *out)
+{
+    return chasm_oracle_global_line_bc(N, h, 0, alpha, phi, out);
+}
+
+/* The same with the boundary rows of chasm_oracle_global_inverse (bc 0 natural,
+ * bc 1 Neumann). */
+int chasm_oracle_global_line_bc(int N, double h, int bc, double alpha, const double *phi, double *out)
 {
     int n = N + 2;
     double *inv = (double *)malloc((size_t)n * n * sizeof(double));
     double *eta = (double *)malloc((size_t)n * sizeof(double));
     if (!inv || !eta) { free(inv); free(eta); return -2; }
-    int rc = chasm_oracle_natural_inverse(N, h, inv);
+    int rc = chasm_oracle_global_inverse(N, h, bc, inv);
     if (rc) { free(inv); free(eta); return rc; }
     for (int u = 0; u < n; ++u) {
         double s = 0.0;

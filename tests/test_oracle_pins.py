@@ -367,3 +367,35 @@ def test_reduce_closed_forms_and_numpy():
     k3 = grid.k_axis(2)[:, None, None, None, None, None]
     assert r[2] == pytest.approx(V * (x1 * f).sum(), rel=1e-13)
     assert r[7] == pytest.approx(V * (k3 * f).sum(), rel=1e-13)
+
+
+# --------------------------------------------------------------------------- Neumann closure
+def test_neumann_global_spline_is_scipys_zero_slope_clamped_spline():
+    """The Neumann global spline (Hermite rows of eq. 2.13 with zero end slopes) equals
+    scipy's clamped cubic spline with zero first derivatives, at any shift."""
+    from scipy.interpolate import CubicSpline
+    rng = np.random.default_rng(11)
+    for N, h in ((9, 0.5), (16, 1.0), (23, 0.3)):
+        x = np.arange(N) * h
+        phi = rng.standard_normal(N)
+        cs = CubicSpline(x, phi, bc_type=((1, 0.0), (1, 0.0)))
+        for a in (0.0, 0.37, -0.81, 1.6):
+            y = x - a * h
+            inside = (y >= x[0]) & (y <= x[-1])
+            got = oracle.global_line(N, h, a, phi, bc=1)
+            assert np.max(np.abs(got[inside] - cs(y[inside]))) < 1e-12
+
+
+def test_neumann_stencils_end_rows_vanish_and_full_window_is_global():
+    rng = np.random.default_rng(12)
+    N, M, h = 16, 8, 0.5
+    c = oracle.stencils(N, M, N - 1, h, oracle.NEUMANN)
+    assert np.all(c[0] == 0.0) and np.all(c[-1] == 0.0)           # s'(x_0) = s'(x_{N-1}) = 0 exactly
+    for a in (0.3, -0.7, 1.2):
+        phi = rng.standard_normal(N)
+        got = oracle.line(N, M, N - 1, h, a, phi, closure=oracle.NEUMANN)
+        assert np.max(np.abs(got - oracle.global_line(N, h, a, phi, bc=1))) < 1e-13
+    # truncated rows approach the untruncated ones geometrically (|sqrt3 - 2| per node)
+    full = oracle.stencils(32, 8, 31, h, oracle.NEUMANN)
+    errs = [np.max(np.abs(oracle.stencils(32, 8, g, h, oracle.NEUMANN) - full)) for g in (4, 6, 8)]
+    assert errs[0] / errs[1] > 10 and errs[1] / errs[2] > 10

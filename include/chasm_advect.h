@@ -64,7 +64,12 @@ typedef enum {
      * makes them exact for cubic data, and outer ghost coefficients extrapolated by a
      * zero fourth difference, so cubic polynomials in x are advected exactly.
      * Needs ghost >= 3. */
-    CHASM_CLOSURE_POLY3 = 1
+    CHASM_CLOSURE_POLY3 = 1,
+    /* The paper's PMBC with the Neumann global condition instead of the natural one:
+     * rows of the inverse of the global matrix with the Hermite boundary rows of
+     * eq. 2.13 and zero end slopes, truncated to |j - I| <= ghost; the slopes at both
+     * line ends are 0. */
+    CHASM_CLOSURE_NEUMANN = 2
 } chasm_closure;
 
 typedef enum {

@@ -30,6 +30,27 @@ def sources():
     return [os.path.join(CSRC, f) for f in units] + [os.path.join(CSRC, "chasm_tables.cpp")]
 
 
+def _deps(src: str, seen=None) -> set:
+    """The source and every local header it includes, transitively."""
+    import re
+    seen = seen if seen is not None else set()
+    if src in seen or not os.path.exists(src):
+        return seen
+    seen.add(src)
+    with open(src) as fh:
+        for inc in re.findall(r'#include\s+"([^"]+)"', fh.read()):
+            _deps(os.path.normpath(os.path.join(os.path.dirname(src), inc)), seen)
+    return seen
+
+
+def _stale(src: str) -> bool:
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in _deps(src))
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
     cmd = ["hipcc", "-c"] + HIPFLAGS + [src, "-o", obj]
@@ -39,12 +60,16 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
+def build(jobs: int | None = None, verbose: bool = True, incremental: bool = False) -> str:
+    """Compile every unit (or, when incremental, only units whose source or local
+    headers are newer than their object) and link the library."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sources()
-    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 4)))
+    todo = [s for s in srcs if _stale(s)] if incremental else srcs
+    jobs = jobs or min(max(len(todo), 1), max(1, min(16, os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(OBJ, os.path.basename(s) + ".o") for s in srcs]
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -52,9 +77,10 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
     os.replace(tmp, LIB)
     if verbose:
-        print(f"built {LIB} from {len(srcs)} units")
+        print(f"built {LIB} from {len(srcs)} units ({len(todo)} compiled)")
     return LIB
 
 
 if __name__ == "__main__":
-    build(int(sys.argv[1]) if len(sys.argv) > 1 else None)
+    args = [a for a in sys.argv[1:] if a != "--incremental"]
+    build(int(args[0]) if args else None, incremental="--incremental" in sys.argv)

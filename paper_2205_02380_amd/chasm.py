@@ -22,13 +22,13 @@ LIB_PATH = os.path.join(_HERE, "libchasm.so")
 
 CHASM_OK, CHASM_EINVAL, CHASM_ENOMEM, CHASM_EDEVICE, CHASM_ESTATE, CHASM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CHASM_F32, CHASM_F64 = 0, 1
-CHASM_CLOSURE_PMBC, CHASM_CLOSURE_POLY3 = 0, 1
+CHASM_CLOSURE_PMBC, CHASM_CLOSURE_POLY3, CHASM_CLOSURE_NEUMANN = 0, 1, 2
 CHASM_SCHED_AUTO, CHASM_SCHED_CUBE, CHASM_SCHED_SLAB, CHASM_SCHED_PLAIN = 0, 1, 2, 3
 CHASM_FLAG_REDUCE_EACH_STEP, CHASM_FLAG_GRAPH = 1, 2
 
 SCHEDULES = {"auto": 0, "cube": 1, "slab": 2, "plain": 3}
 SCHEDULE_NAMES = {v: k for k, v in SCHEDULES.items()}
-CLOSURES = {"pmbc": 0, "poly3": 1}
+CLOSURES = {"pmbc": 0, "poly3": 1, "neumann": 2}
 NRED = 8
 DIAG_NAMES = ("mass", "l2", "x1", "x2", "x3", "k1", "k2", "k3")
 
@@ -284,7 +284,7 @@ def compiled_shapes(sizes=(8, 16, 24, 32, 48, 64)) -> list:
     for n in sizes:
         grid = Grid((n, n, n), (0.0,) * 3, (float(n),) * 3, (1, 1, 1), (0.0,) * 3, (1.0,) * 3)
         for dt in ("f32", "f64"):
-            for cl in ("pmbc", "poly3"):
+            for cl in ("pmbc", "poly3", "neumann"):
                 for m in range(2, n + 1):
                     for g in range(1, n):
                         if supported(grid, m, g, 0.0, dt, cl):

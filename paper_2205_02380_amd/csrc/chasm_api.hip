@@ -183,7 +183,7 @@ static chasm_status validate(const chasm_advect_desc* d, const KernelSet** ks_ou
     if (d->ghost < 1) return fail(CHASM_EINVAL, "ghost must be >= 1");
     if (!std::isfinite(d->dt)) return fail(CHASM_EINVAL, "dt must be finite");
     if (d->dtype != CHASM_F32 && d->dtype != CHASM_F64) return fail(CHASM_EINVAL, "unknown dtype");
-    if (d->closure != CHASM_CLOSURE_PMBC && d->closure != CHASM_CLOSURE_POLY3)
+    if (d->closure != CHASM_CLOSURE_PMBC && d->closure != CHASM_CLOSURE_POLY3 && d->closure != CHASM_CLOSURE_NEUMANN)
         return fail(CHASM_EINVAL, "unknown closure");
     if (d->closure == CHASM_CLOSURE_POLY3 && d->ghost < 3) return fail(CHASM_EINVAL, "POLY3 closure needs ghost >= 3");
     if (d->nbatch < 1) return fail(CHASM_EINVAL, "nbatch must be >= 1");

@@ -94,46 +94,15 @@ __device__ __forceinline__ void vset<double>(double2& v, int i, double x)
 // offset (VGPR) and a uniform byte offset (SGPR), so a strided line needs no
 // per-element 64-bit address registers.  Out-of-range accesses load 0 and drop
 // stores (hardware range check against the resource size).
-// Cache policy of the field's loads and stores: every field value is read once and
-// written once per launch, so they are streamed (the nontemporal bit of the buffer
-// intrinsics' aux operand; 0 would be default caching).  Measured on C3: the x3
-// pencil pass is 5 % faster streamed; C2 is unchanged; results are bitwise equal.
+// Cache policy of the field's buffer loads and stores (k_cube, k_pencil): every field
+// value is read once and written once per launch, so they are streamed (the
+// nontemporal bit of the buffer intrinsics' aux operand; 0 would be default caching).
+// Measured: the x3 pencil pass on C3 is 8 % faster streamed, C2 is unchanged, results
+// are bitwise equal.  The slab kernel keeps default caching (streaming its strided
+// scalar stores raised its write traffic by 4 %).
 #ifndef CHASM_FIELD_CPOL
 #define CHASM_FIELD_CPOL 2
 #endif
-
-// Streamed 16-byte and scalar field accesses through plain pointers (same policy).
-template <typename V>
-__device__ __forceinline__ V ld_stream(const V* p)
-{
-    if constexpr (CHASM_FIELD_CPOL != 0) {
-        using E = decltype(p->x);
-        using X = E __attribute__((ext_vector_type(sizeof(V) / sizeof(E))));
-        const X v = __builtin_nontemporal_load(reinterpret_cast<const X*>(p));
-        return __builtin_bit_cast(V, v);
-    } else {
-        return *p;
-    }
-}
-template <typename V>
-__device__ __forceinline__ void st_stream(V* p, const V& x)
-{
-    if constexpr (CHASM_FIELD_CPOL != 0) {
-        using E = decltype(p->x);
-        using X = E __attribute__((ext_vector_type(sizeof(V) / sizeof(E))));
-        __builtin_nontemporal_store(__builtin_bit_cast(X, x), reinterpret_cast<X*>(p));
-    } else {
-        *p = x;
-    }
-}
-template <typename T>
-__device__ __forceinline__ void st_stream_scalar(T* p, T x)
-{
-    if constexpr (CHASM_FIELD_CPOL != 0)
-        __builtin_nontemporal_store(x, p);
-    else
-        *p = x;
-}
 
 struct Buf {
     __amdgpu_buffer_rsrc_t r;
@@ -442,7 +411,7 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
     const V* __restrict__ src = reinterpret_cast<const V*>(base_ptr);
 #pragma unroll
     for (int e = threadIdx.x; e < S * N * N / VW; e += NT) {
-        const V x = ld_stream(src + e);
+        const V x = src[e];
         const int row = (e * VW) / N, x1 = (e * VW) % N;
 #pragma unroll
         for (int i = 0; i < VW; ++i) lds[row * PX + x1 + i] = vget<T>(x, i);
@@ -470,7 +439,7 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
             V x;
 #pragma unroll
             for (int i = 0; i < VW; ++i) vset<T>(x, i, lds[row * PX + x1 + i]);
-            st_stream(dst + e, x);
+            dst[e] = x;
         }
     } else {
         int sigma;
@@ -482,8 +451,7 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
             T v[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
-            advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma,
-                                                              [&](int j, T x) { st_stream_scalar(out + j * N, x); });
+            advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { out[j * N] = x; });
         });
     }
 }

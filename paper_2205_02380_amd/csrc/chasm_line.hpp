@@ -82,7 +82,8 @@ struct PatchLU {
 // for 0 < i < N-1, eta_{-1} = 2 eta_0 - eta_1, eta_N = 2 eta_{N-1} - eta_{N-2}, and
 // h s'(x_I) = (eta_{I+1} - eta_{I-1}) / 2.  Closure CL = 1 adds the minimum-norm
 // correction that makes each truncated row exact for cubics (normal equations on the
-// scaled monomials ((j-I)/G)^q, q = 0..3).  All in FP64 at compile time.
+// scaled monomials ((j-I)/G)^q, q = 0..3).  CL = 2 takes the rows of the Neumann
+// global spline instead (see neumann()).  All in FP64 at compile time.
 template <int N, int M, int G, int CL>
 struct Stencil {
     static constexpr int P = Shape<N, M>::P;
@@ -90,6 +91,10 @@ struct Stencil {
     double c[P + 1][W] = {};
     constexpr Stencil()
     {
+        if constexpr (CL == 2) {
+            neumann();
+            return;
+        }
         constexpr int n = N - 2;
         double cp[N] = {}, den[N] = {};
         for (int i = 0; i < n; ++i) {
@@ -151,6 +156,37 @@ struct Stencil {
                     const double u = (double)(t - G) / G;
                     c[q][t] += lam[0] + u * (lam[1] + u * (lam[2] + u * lam[3]));
                 }
+            }
+        }
+    }
+
+    // CL = 2: the Neumann condition (eq. 2.13 with zero end slopes) gives eta_{-1} =
+    // eta_1 and eta_N = eta_{N-2}; with the interpolation rows the unknowns eta_0..eta_{N-1}
+    // solve the tridiagonal system [4 2; 1 4 1; ...; 2 4] eta = 6 phi (Thomas, per unit
+    // data vector).  The slopes at both line ends are then exactly 0.
+    constexpr void neumann()
+    {
+        double cp[N] = {}, den[N] = {};
+        for (int i = 0; i < N; ++i) {
+            const double sub = i == N - 1 ? 2.0 : 1.0, sup = i == 0 ? 2.0 : 1.0;
+            den[i] = 4.0 - (i > 0 ? sub * cp[i - 1] : 0.0);
+            cp[i] = sup / den[i];
+        }
+        for (int j = 0; j < N; ++j) {
+            double eta[N + 2] = {}, y[N] = {};
+            for (int i = 0; i < N; ++i) {
+                const double sub = i == N - 1 ? 2.0 : 1.0;
+                const double r = (i == j) ? 6.0 : 0.0;
+                y[i] = (r - (i > 0 ? sub * y[i - 1] : 0.0)) / den[i];
+            }
+            for (int i = N - 2; i >= 0; --i) y[i] -= cp[i] * y[i + 1];
+            for (int i = 0; i < N; ++i) eta[i + 1] = y[i];
+            eta[0] = eta[2];
+            eta[N + 1] = eta[N - 1];
+            for (int q = 0; q <= P; ++q) {
+                const int I = Shape<N, M>::iface(q);
+                const int t = j - I + G;
+                if (t >= 0 && t < W) c[q][t] = 0.5 * (eta[I + 2] - eta[I]);
             }
         }
     }

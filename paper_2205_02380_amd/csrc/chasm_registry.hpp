@@ -35,19 +35,19 @@ const KernelSet* kernel_set();
 // FP32: the benchmark and serving grids, the autotuner's patch x ghost sweep for the
 // 32^3 / 48^3 / 64^3 grids, and the test shapes.  FP64: the plain FP64 form and the
 // FP64 parity cases.
-#define CHASM_SHAPES_N8_F32(X) X(float, 8, 2, 1, 0) X(float, 8, 4, 3, 0) X(float, 8, 8, 7, 0)
-#define CHASM_SHAPES_N8_F64(X) X(double, 8, 2, 1, 0) X(double, 8, 4, 3, 0) X(double, 8, 8, 7, 0)
+#define CHASM_SHAPES_N8_F32(X) X(float, 8, 2, 1, 0) X(float, 8, 4, 3, 0) X(float, 8, 8, 7, 0) X(float, 8, 4, 3, 2)
+#define CHASM_SHAPES_N8_F64(X) X(double, 8, 2, 1, 0) X(double, 8, 4, 3, 0) X(double, 8, 8, 7, 0) X(double, 8, 4, 3, 2)
 #define CHASM_SHAPES_N16_F32(X)                                                                        \
     X(float, 16, 8, 4, 0) X(float, 16, 8, 4, 1) X(float, 16, 8, 6, 0) X(float, 16, 4, 8, 0)              \
-    X(float, 16, 8, 15, 0) X(float, 16, 16, 5, 0)
+    X(float, 16, 8, 15, 0) X(float, 16, 16, 5, 0) X(float, 16, 8, 4, 2)
 #define CHASM_SHAPES_N16_F64(X)                                                                        \
     X(double, 16, 8, 4, 0) X(double, 16, 8, 4, 1) X(double, 16, 8, 6, 0) X(double, 16, 4, 8, 0)          \
-    X(double, 16, 8, 15, 0) X(double, 16, 16, 5, 0)
+    X(double, 16, 8, 15, 0) X(double, 16, 16, 5, 0) X(double, 16, 8, 4, 2)
 #define CHASM_SHAPES_N24_F32(X) X(float, 24, 8, 6, 0) X(float, 24, 12, 6, 0)
 #define CHASM_SHAPES_N24_F64(X) X(double, 24, 8, 6, 0) X(double, 24, 12, 6, 0)
 #define CHASM_SHAPES_N32_F32(X)                                                                        \
     X(float, 32, 8, 4, 0) X(float, 32, 8, 6, 0) X(float, 32, 8, 8, 0) X(float, 32, 16, 4, 0)             \
-    X(float, 32, 16, 6, 0) X(float, 32, 16, 8, 0)
+    X(float, 32, 16, 6, 0) X(float, 32, 16, 8, 0) X(float, 32, 8, 6, 2)
 #define CHASM_SHAPES_N32_F64(X) X(double, 32, 8, 6, 0) X(double, 32, 16, 8, 0)
 #define CHASM_SHAPES_N48_F32(X)                                                                        \
     X(float, 48, 8, 4, 0) X(float, 48, 8, 6, 0) X(float, 48, 8, 8, 0) X(float, 48, 12, 4, 0)             \

@@ -48,6 +48,36 @@ bool natural_slope_rows(int N, double h, const std::vector<int>& ifaces, std::ve
     return true;
 }
 
+// The Neumann condition (eq. 2.13 with zero end slopes): eta_{-1} = eta_1 and eta_N =
+// eta_{N-2}, so eta_0..eta_{N-1} solve [4 2; 1 4 1; ...; 2 4] eta = 6 phi, a strictly
+// diagonally dominant tridiagonal system; the slopes at both ends are 0.
+bool neumann_slope_rows(int N, double h, const std::vector<int>& ifaces, std::vector<double>& out)
+{
+    if (N < 2 || !(h > 0.0)) return false;
+    std::vector<double> cp(N), den(N), y(N), eta(N + 2);
+    for (int i = 0; i < N; ++i) {
+        const double sub = i == N - 1 ? 2.0 : 1.0, sup = i == 0 ? 2.0 : 1.0;
+        den[i] = 4.0 - (i > 0 ? sub * cp[i - 1] : 0.0);
+        cp[i] = sup / den[i];
+    }
+    out.assign(ifaces.size() * (size_t)N, 0.0);
+    for (int j = 0; j < N; ++j) {
+        for (int i = 0; i < N; ++i) {
+            const double sub = i == N - 1 ? 2.0 : 1.0;
+            y[i] = ((i == j ? 6.0 : 0.0) - (i > 0 ? sub * y[i - 1] : 0.0)) / den[i];
+        }
+        for (int i = N - 2; i >= 0; --i) y[i] -= cp[i] * y[i + 1];
+        for (int i = 0; i < N; ++i) eta[i + 1] = y[i];
+        eta[0] = eta[2];
+        eta[N + 1] = eta[N - 1];
+        for (size_t q = 0; q < ifaces.size(); ++q) {
+            const int I = ifaces[q];
+            out[q * N + j] = (eta[I + 2] - eta[I]) / (2.0 * h);
+        }
+    }
+    return true;
+}
+
 // Minimum-norm correction of one stencil row so that it differentiates cubics
 // exactly: sum_j c_j (j-I)^q = delta_{q1}/h, q = 0..3.  With V_jq = ((j-I)/g)^q the
 // conditions read V^T c = e, e = (0, 1/(g h), 0, 0); the correction is
@@ -128,8 +158,8 @@ bool build_axis_tables(int N, int M, int g, int G, double h, int closure, int nk
     std::vector<int> ifaces(P + 1);
     for (int q = 0; q <= P; ++q) ifaces[q] = q < P ? q * M : N - 1;
     std::vector<double> rows;
-    if (!natural_slope_rows(N, h, ifaces, rows)) {
-        err = "axis tables: natural spline solve failed";
+    if (!(closure == 2 ? neumann_slope_rows(N, h, ifaces, rows) : natural_slope_rows(N, h, ifaces, rows))) {
+        err = "axis tables: global spline solve failed";
         return false;
     }
     out.stencil.assign((size_t)(P + 1) * W, 0.0);

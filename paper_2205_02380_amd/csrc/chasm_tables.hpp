@@ -29,7 +29,11 @@ inline int npatch(int N, int M) { return (N - 1 + M - 1) / M; }
 // out[(N)*q + j] for each requested interface I_q.  Returns false on bad input.
 bool natural_slope_rows(int N, double h, const std::vector<int>& ifaces, std::vector<double>& out);
 
-// Build every table of one axis.  closure: 0 paper PMBC, 1 cubic-exact variant.
+// The same for the Neumann global spline (zero slopes at both ends).
+bool neumann_slope_rows(int N, double h, const std::vector<int>& ifaces, std::vector<double>& out);
+
+// Build every table of one axis.  closure: 0 paper PMBC, 1 cubic-exact variant,
+// 2 Neumann global spline.
 bool build_axis_tables(int N, int M, int g, int G, double h, int closure, int nk, double k_lo, double hk,
                        double dt, AxisTables& out, std::string& err);
 

@@ -20,7 +20,7 @@
 //   A  k1 forward for every (k2, k3) line          -> W1[m][k3][k2]
 //   B  k2 forward (zero-padded, P outputs)          -> W2[m][xi2][k3]
 //   C  k3 forward, times That(xi1, xi2, .), inverse, first N_k outputs (in place)
-//   D  k2 inverse, first N_k outputs                -> W1[m][k3][k2]
+//   D  k2 inverse, first N_k outputs                -> W1[m][k3][k2] + W1o[m][k3][k2]
 //   E  k1 inverse of the chunk, into the accumulator of each (k2, k3) line
 // Rows of W1 and W2 are padded to N_k + 1 complex values, so the row-per-lane stages
 // (B reads, C, D writes) and the column-per-lane stages (A, B writes, D reads, E) are
@@ -96,13 +96,15 @@ struct ThetaShape {
     static constexpr int P = 2 * NK;
     static constexpr int C = P / R;          // xi1 values per chunk
     static constexpr int RS = NK + 1;        // padded row length (complex)
-    static constexpr int W1N = C * NK * RS;
+    static constexpr int W1N = C * NK * RS;     // W1 and its odd-half twin W1o
     static constexpr int W2N = C * P * RS;
     static_assert(P % R == 0, "chunks");
     static_assert(C <= NK ? NK % C == 0 : C == 2 * NK, "chunk length");
 };
 
-template <typename T, int NK, int R, int NT, int WPE = 1>
+// SPLIT: stages B and D as two half-transform work items per line (else one item per
+// line; measured 3 % slower at N_k = 16).
+template <typename T, int NK, int R, int NT, int WPE = 1, bool SPLIT = true>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_theta(T* __restrict__ fx, const double* __restrict__ that, const ThetaArgs a,
                                              long long total)
 {
@@ -115,6 +117,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     constexpr int LPT = LA >= NT ? LA / NT : 1;
     static_assert(LA < NT || LA % NT == 0, "whole k1 lines per thread");
     __shared__ cd W1[S::W1N];
+    __shared__ cd W1o[SPLIT ? S::W1N : 1];
     __shared__ cd W2[S::W2N];
     __shared__ cd E[3][NK];
 
@@ -187,19 +190,39 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                     }
                 });
                 __syncthreads();
-                // ---- B: k2 forward, zero-padded to P
-                for (int ln = tid; ln < LB; ln += NT) {
-                    const int m = ln / NK, q3 = ln % NK;
-                    cd row[NK], Y[P];
-                    sfor<0, NK>([&](auto jc) {
-                        constexpr int j = decltype(jc)::value;
-                        row[j] = W1[(m * NK + q3) * RS + j];
-                    });
-                    fft_fwd_padded<NK>(row, Y);
-                    sfor<0, P>([&](auto fc) {
-                        constexpr int f = decltype(fc)::value;
-                        W2[(m * P + f) * RS + q3] = Y[f];
-                    });
+                // ---- B: k2 forward, zero-padded to P.  The two halves of a line (even
+                // and odd outputs: transforms of x_j and of x_j w^j) go to two work items,
+                // so 2 LB items keep every thread busy; h is uniform across a wave.
+                if constexpr (SPLIT) {
+                    for (int it = tid; it < 2 * LB; it += NT) {
+                        const int h = it / LB, ln = it % LB;
+                        const int m = ln / NK, q3 = ln % NK;
+                        cd row[NK];
+                        sfor<0, NK>([&](auto jc) {
+                            constexpr int j = decltype(jc)::value;
+                            const cd x = W1[(m * NK + q3) * RS + j];
+                            row[j] = h ? tmul<j, P, -1>(x) : x;
+                        });
+                        transform<NK, -1>(row);
+                        sfor<0, NK>([&](auto fc) {
+                            constexpr int f = decltype(fc)::value;
+                            W2[(m * P + 2 * f + h) * RS + q3] = row[f];
+                        });
+                    }
+                } else {
+                    for (int ln = tid; ln < LB; ln += NT) {
+                        const int m = ln / NK, q3 = ln % NK;
+                        cd row[NK], Y[P];
+                        sfor<0, NK>([&](auto jc) {
+                            constexpr int j = decltype(jc)::value;
+                            row[j] = W1[(m * NK + q3) * RS + j];
+                        });
+                        fft_fwd_padded<NK>(row, Y);
+                        sfor<0, P>([&](auto fc) {
+                            constexpr int f = decltype(fc)::value;
+                            W2[(m * P + f) * RS + q3] = Y[f];
+                        });
+                    }
                 }
                 __syncthreads();
                 // ---- C: k3 forward, symbol, inverse (first NK outputs), in place
@@ -225,19 +248,39 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                     });
                 }
                 __syncthreads();
-                // ---- D: k2 inverse, first NK outputs
-                for (int ln = tid; ln < LB; ln += NT) {
-                    const int m = ln / NK, q3 = ln % NK;
-                    cd col[P], o[NK];
-                    sfor<0, P>([&](auto fc) {
-                        constexpr int f = decltype(fc)::value;
-                        col[f] = W2[(m * P + f) * RS + q3];
-                    });
-                    fft_inv_half<NK>(col, o);
-                    sfor<0, NK>([&](auto jc) {
-                        constexpr int j = decltype(jc)::value;
-                        W1[(m * NK + q3) * RS + j] = o[j];
-                    });
+                // ---- D: k2 inverse, first NK outputs, as two halves: the inverse of the
+                // even inputs into W1, the inverse of the odd inputs times w^-j into W1o
+                // (stage E adds them)
+                if constexpr (SPLIT) {
+                    for (int it = tid; it < 2 * LB; it += NT) {
+                        const int h = it / LB, ln = it % LB;
+                        const int m = ln / NK, q3 = ln % NK;
+                        cd col[NK];
+                        sfor<0, NK>([&](auto fc) {
+                            constexpr int f = decltype(fc)::value;
+                            col[f] = W2[(m * P + 2 * f + h) * RS + q3];
+                        });
+                        transform<NK, +1>(col);
+                        cd* dst = h ? W1o : W1;
+                        sfor<0, NK>([&](auto jc) {
+                            constexpr int j = decltype(jc)::value;
+                            dst[(m * NK + q3) * RS + j] = h ? tmul<j, P, +1>(col[j]) : col[j];
+                        });
+                    }
+                } else {
+                    for (int ln = tid; ln < LB; ln += NT) {
+                        const int m = ln / NK, q3 = ln % NK;
+                        cd col[P], o[NK];
+                        sfor<0, P>([&](auto fc) {
+                            constexpr int f = decltype(fc)::value;
+                            col[f] = W2[(m * P + f) * RS + q3];
+                        });
+                        fft_inv_half<NK>(col, o);
+                        sfor<0, NK>([&](auto jc) {
+                            constexpr int j = decltype(jc)::value;
+                            W1[(m * NK + q3) * RS + j] = o[j];
+                        });
+                    }
                 }
                 __syncthreads();
                 // ---- E: k1 inverse of this chunk, demodulated, into the real result
@@ -250,7 +293,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                         cd v[C];
                         sfor<0, C>([&](auto mc) {
                             constexpr int m = decltype(mc)::value;
-                            v[m] = W1[(m * NK + k3) * RS + k2];
+                            v[m] = SPLIT ? cadd(W1[(m * NK + k3) * RS + k2], W1o[(m * NK + k3) * RS + k2])
+                                         : W1[(m * NK + k3) * RS + k2];
                         });
                         auto put = [&](auto kc, cd x) {
                             constexpr int k = decltype(kc)::value;

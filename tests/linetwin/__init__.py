@@ -16,7 +16,8 @@ LIB = os.path.join(HERE, "liblinetwin.so")
 # (N, M, G, closure) compiled into the twin
 SHAPES = [(8, 2, 1, 0), (8, 4, 3, 0), (8, 4, 3, 1), (8, 8, 7, 0), (8, 8, 7, 1), (16, 8, 4, 0), (16, 8, 4, 1),
           (16, 8, 15, 0), (16, 5, 6, 0), (16, 5, 6, 1), (24, 8, 6, 0), (24, 8, 6, 1), (32, 8, 6, 0), (32, 8, 6, 1),
-          (48, 16, 8, 0), (48, 16, 8, 1), (64, 16, 8, 0), (64, 16, 8, 1), (61, 15, 8, 0), (61, 15, 8, 1)]
+          (48, 16, 8, 0), (48, 16, 8, 1), (64, 16, 8, 0), (64, 16, 8, 1), (61, 15, 8, 0), (61, 15, 8, 1),
+          (8, 4, 3, 2), (16, 8, 4, 2), (16, 8, 15, 2), (32, 8, 6, 2), (61, 15, 8, 2)]
 
 
 def build() -> str:

@@ -49,7 +49,7 @@ static int rows(double* out)
     X(8, 2, 1, 0) X(8, 4, 3, 0) X(8, 4, 3, 1) X(8, 8, 7, 0) X(8, 8, 7, 1) X(16, 8, 4, 0) X(16, 8, 4, 1)    \
     X(16, 8, 15, 0) X(16, 5, 6, 0) X(16, 5, 6, 1) X(24, 8, 6, 0) X(24, 8, 6, 1) X(32, 8, 6, 0)            \
     X(32, 8, 6, 1) X(48, 16, 8, 0) X(48, 16, 8, 1) X(64, 16, 8, 0) X(64, 16, 8, 1) X(61, 15, 8, 0)        \
-    X(61, 15, 8, 1)
+    X(61, 15, 8, 1) X(8, 4, 3, 2) X(16, 8, 4, 2) X(16, 8, 15, 2) X(32, 8, 6, 2) X(61, 15, 8, 2)
 
 // One sweep of one line with shift alpha = k dt / h for the single k = klo.
 extern "C" int twin_line(int fp64, int N, int M, int G, int CL, double h, double klo, double dt,

@@ -1,4 +1,5 @@
-"""Every compiled kernel shape (dtype, N, M, ghost, closure) against the FP64 oracle,
+"""Every compiled kernel shape (dtype, N, M, ghost, closure: the paper's PMBC, its
+Neumann-condition variant and the cubic-exact variant) against the FP64 oracle,
 under every schedule the shape supports, on a small ragged k grid whose shifts take
 both signs, zero and |alpha| > 1.  This covers each candidate the autotuner may pick
 (C3: N = 48, M in {8, 12, 16}, g in {4, 6, 8}; C4: N = 64, M in {8, 16}, g in {4, 6, 8})."""
@@ -34,9 +35,9 @@ def test_compiled_shape_matches_oracle(dtype, N, M, g, closure):
     if dtype == "f32":
         f0 = f0.astype(np.float32).astype(np.float64)
     steps = 2
-    cl = oracle.POLY3 if closure == "poly3" else oracle.PMBC
+    cl = {"pmbc": oracle.PMBC, "poly3": oracle.POLY3, "neumann": oracle.NEUMANN}[closure]
     ref = oracle.advect6d(f0, grid.nx, grid.hx, grid.nk, grid.k_lo, grid.hk, (M,) * 3, g, dt, steps, closure=cl)
-    tol = 1e-5 if dtype == "f32" else (1e-12 if closure == "pmbc" else 1e-10)
+    tol = 1e-5 if dtype == "f32" else (1e-10 if closure == "poly3" else 1e-12)
     tdt = torch.float32 if dtype == "f32" else torch.float64
     scale = np.max(np.abs(ref))
     ran = []

@@ -107,7 +107,7 @@ def test_product_line_algebra_matches_oracle_fp64(N, M, G, CL):
     h = 0.7
     # cubic-exact rows at g = 3 are an exactly determined 4-node Vandermonde solve:
     # both sides hold them to ~1e-12
-    tol = 1e-13 if CL == 0 else 2e-11
+    tol = 1e-13 if CL != 1 else 2e-11
     for a in ALPHAS:
         phi = rng.standard_normal(N)
         ref = oracle.line(N, M, G, h, a, phi, closure=CL)
@@ -123,7 +123,7 @@ def test_compile_time_rows_match_host_tables_and_oracle(N, M, G, CL):
     ct = linetwin.rows(N, M, G, CL)
     host = linetwin.rows(N, M, G, CL, h=h)
     orc = oracle.stencils(N, M, G, h, CL) * h
-    tol = 1e-14 if CL == 0 else 1e-11
+    tol = 1e-14 if CL != 1 else 1e-11
     assert np.max(np.abs(ct - host)) < tol
     P = ct.shape[0] - 1
     for q in range(P + 1):

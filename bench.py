@@ -334,6 +334,67 @@ def bench_lpc1(args):
     }
 
 
+def bench_ho2d(args):
+    """The 2-D harmonic oscillator of Sec. 5.1 on the paper's grid and time step: x on
+    [-12, 12] with dx = 0.1 (241 nodes, 4 patches, n_nb = 20), k on [-6.4, 6.4) with
+    dk = 0.025 (512 nodes), omega = (pi/5)^2, tau = 2e-5, 300000 LPC1 steps (t = 6),
+    against the exact phase-space rotation."""
+    import math
+
+    import torch
+    from oracle import ho2d as oho
+    from paper_2205_02380_amd import ho2d
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    W = (math.pi / 5.0) ** 2
+    nx, hx, nk, hk, tau = 241, 0.1, 512, 0.025, 0.00002
+    steps = args.steps if args.steps != 100 else 300000
+    x, k = oho.axes(nx, -12.0, hx, nk, -6.4, hk)
+    f0 = oho.f0(x[None, :], k[:, None])
+    f = torch.tensor(f0, dtype=torch.float64, device=dev)
+    s = ho2d.HO2D(f, nx, -12.0, hx, nk, -6.4, hk, 60, 20, W, tau, stream=stream)
+    g = torch.tensor(f0, dtype=torch.float64, device=dev)
+    w = ho2d.HO2D(g, nx, -12.0, hx, nk, -6.4, hk, 60, 20, W, tau, stream=stream)
+    w.step(args.warmup)
+    w.close()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    s.close()
+    total_s = e0.elapsed_time(e1) / 1e3
+    got = f.cpu().numpy()
+    ex = oho.exact(x, k, steps * tau, W)
+    err_inf = float(np.max(np.abs(got - ex)))
+    err_2 = float(np.sqrt(np.sum((got - ex) ** 2) * hx * hk))
+    mass_dev = float(abs(got.sum() - f0.sum()) * hx * hk)
+    cpu = None
+    if not args.no_cpu:
+        n = 10
+        t0 = time.perf_counter()
+        oho.lpc1(f0, x, k, hx, hk, 60, 20, W, tau, n)
+        tc = time.perf_counter() - t0
+        cpu = {"value": nx * nk * n / tc, "unit": "point-updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n} LPC1 steps of the same grid ({tc:.1f} s; C line oracle + numpy FFT, FP64)"}
+    pts = nx * nk
+    flops = 2 * 2 * nk * nk * nx * steps                   # the two k-derivative contractions per step
+    return {
+        "metric": "2-D harmonic-oscillator LPC1 point-updates/s (FP64) and eps_inf(T=10) vs the exact rotation",
+        "value": pts * steps / total_s, "unit": "point-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": total_s * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "analytic initial packet of Sec. 5.1",
+        "config": {"workload": "ho2d: x 241 nodes dx 0.1 on [-12,12], k 512 nodes dk 0.025 on [-6.4,6.4), "
+                               "4 patches, n_nb 20, omega (pi/5)^2, tau 2e-5, T = steps x tau"},
+        "accuracy": {"eps_inf": err_inf, "eps_2": err_2, "mass_deviation": mass_dev, "t": steps * tau},
+        "roofline": {"bound": "launch", "achieved": flops / total_s / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": flops / total_s / 1e12 / 78.6, "traffic": None,
+                     "kernel": "whole step (5 launches of a 123k-point problem: launch-bound)"},
+        "cpu_baseline": cpu,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -343,7 +404,7 @@ def main():
     ap.add_argument("--cpu-kpoints", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "serving", "theta", "lpc1"])
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "serving", "theta", "lpc1", "ho2d"])
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -381,6 +442,9 @@ def main():
         return
     if args.workload == "lpc1":
         print(json.dumps(bench_lpc1(args)), flush=True)
+        return
+    if args.workload == "ho2d":
+        print(json.dumps(bench_ho2d(args)), flush=True)
         return
     w = inputs.workload("C2")
     g = w.grid

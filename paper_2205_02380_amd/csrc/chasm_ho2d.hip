@@ -1,0 +1,354 @@
+// chasm_ho2d.hip -- the 2-D harmonic-oscillator workload of Sec. 5.1 (see
+// include/chasm_ho2d.h): LPC1 with the patched-spline characteristic step in x and the
+// spectral k-derivative Theta[f] = omega x d_k f, all FP64.
+//
+// Kernels:
+//   k_ho_advect  the characteristic step of LB k-lines per block, lines of runtime
+//                length in LDS: PMBC interface slopes (eqs. 3.4-3.5), each patch's
+//                reduced Hermite system solved as a product with its precomputed
+//                inverse (one output per thread, so a line's patches solve in parallel),
+//                the Hermite ghosts, and the 4-tap evaluation by the owning patch
+//                (eqs. 3.7-3.8, Sec. 3.1.3), out of place.
+//   k_ho_theta   out[k][x] = omega x sum_q D[k][q] f[q][x]: a dense FP64 contraction
+//                with the circulant spectral differentiation matrix, 64 x 64 output
+//                tiles staged through LDS, 4 x 4 outputs per thread.
+//   k_ho_combine the predictor / corrector combinations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/chasm_ho2d.h"
+#include "chasm_tables.hpp"
+
+namespace chasm {
+void set_last_error(const std::string& msg);
+
+struct HoArgs {
+    int N, M, P, mlast, g, nk;
+    double hx;
+    const double* stencil;     // (P+1) x (2g+1), slopes (not times h)
+    const double* ainvM;       // (M+1)^2 inverse of [4 2; 1 4 1; ...; 2 4]
+    const double* ainvL;       // (mlast+1)^2
+    const int* shift;          // nk
+    const double* w;           // nk x 4
+};
+
+constexpr int HO_LB = 4;       // lines per block
+
+__global__ __launch_bounds__(256) void k_ho_advect(const double* __restrict__ in, double* __restrict__ out, const HoArgs a,
+                                                  int nlines)
+{
+    extern __shared__ double sm[];
+    const int N = a.N, M = a.M, P = a.P;
+    const int ES = N - 1 + 3 * P;                    // sum over patches of (m + 3)
+    double* phi = sm;                                // [LB][N]
+    double* dsl = phi + HO_LB * N;                   // [LB][P+1] slopes times h
+    double* eta = dsl + HO_LB * (P + 1);             // [LB][ES], patch l at l (M+3): eta_{-1..m+1}
+    const int line0 = blockIdx.x * HO_LB;
+    const int tid = threadIdx.x;
+
+    for (int e = tid; e < HO_LB * N; e += blockDim.x) {
+        const int ln = e / N, L = line0 + ln;
+        phi[e] = L < nlines ? in[(long long)L * N + e % N] : 0.0;
+    }
+    __syncthreads();
+    const int W = 2 * a.g + 1;
+    for (int e = tid; e < HO_LB * (P + 1); e += blockDim.x) {
+        const int ln = e / (P + 1), q = e % (P + 1);
+        const int I = q < P ? q * M : N - 1;
+        double acc = 0.0;
+        for (int t = 0; t < W; ++t) {
+            const int j = I - a.g + t;
+            if (j >= 0 && j < N) acc = fma(a.stencil[q * W + t], phi[ln * N + j], acc);
+        }
+        dsl[e] = acc * a.hx;
+    }
+    __syncthreads();
+    const int per_line = N - 1 + P;                  // unknowns eta_0..eta_m of every patch
+    for (int e = tid; e < HO_LB * per_line; e += blockDim.x) {
+        const int ln = e / per_line, r = e % per_line;
+        const int l = min(r / (M + 1), P - 1);
+        const int i = r - l * (M + 1);
+        const int m = l < P - 1 ? M : a.mlast;
+        const double* A = (l < P - 1 ? a.ainvM : a.ainvL) + (long long)i * (m + 1);
+        const double* ph = phi + ln * N + l * M;
+        const double dl = dsl[ln * (P + 1) + l], dr = dsl[ln * (P + 1) + l + 1];
+        double acc = 0.0;
+        for (int jj = 0; jj <= m; ++jj) {
+            double rhs = 6.0 * ph[jj];
+            if (jj == 0) rhs += 2.0 * dl;
+            if (jj == m) rhs -= 2.0 * dr;
+            acc = fma(A[jj], rhs, acc);
+        }
+        eta[ln * ES + l * (M + 3) + 1 + i] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < HO_LB * P; e += blockDim.x) {
+        const int ln = e / P, l = e % P;
+        const int m = l < P - 1 ? M : a.mlast;
+        double* E = eta + ln * ES + l * (M + 3);
+        E[0] = E[2] - 2.0 * dsl[ln * (P + 1) + l];                // eta_{-1} = eta_1 - 2 h d_L
+        E[m + 2] = E[m] + 2.0 * dsl[ln * (P + 1) + l + 1];        // eta_{m+1} = eta_{m-1} + 2 h d_R
+    }
+    __syncthreads();
+    for (int e = tid; e < HO_LB * N; e += blockDim.x) {
+        const int ln = e / N, j = e % N, L = line0 + ln;
+        if (L >= nlines) continue;
+        const int kk = L % a.nk;
+        const int c = j + a.shift[kk];                           // departure cell
+        double v = 0.0;
+        if (c >= -4 && c <= N + 2) {
+            const int l = c < 0 ? 0 : min(c / M, P - 1);         // owner patch
+            const int m = l < P - 1 ? M : a.mlast;
+            const int nu = c - l * M;
+            const double* E = eta + ln * ES + l * (M + 3);
+            const double* w = a.w + 4 * kk;
+            for (int r = 0; r < 4; ++r) {
+                const int u = nu - 1 + r;                        // eta_u, zero beyond the ghosts
+                if (u >= -1 && u <= m + 1) v = fma(w[r], E[u + 1], v);
+            }
+        }
+        out[(long long)L * N + j] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ho_theta(const double* __restrict__ D, const double* __restrict__ f,
+                                                 double* __restrict__ out, int nk, int nx, double x_lo, double hx,
+                                                 double omega)
+{
+    __shared__ double As[16][65];
+    __shared__ double Bs[16][64];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    double acc[4][4] = {};
+    for (int q0 = 0; q0 < nk; q0 += 16) {
+        for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+            const int rr = e / 16, qq = e % 16;                 // D[r0 + rr][q0 + qq]
+            const int r = r0 + rr, q = q0 + qq;
+            As[qq][rr] = (r < nk && q < nk) ? D[(long long)r * nk + q] : 0.0;
+            const int qb = e / 64, cc = e % 64;                 // f[q0 + qb][c0 + cc]
+            const int qf = q0 + qb, x = c0 + cc;
+            Bs[qb][cc] = (qf < nk && x < nx) ? f[(long long)qf * nx + x] : 0.0;
+        }
+        __syncthreads();
+        for (int qq = 0; qq < 16; ++qq) {
+            double av[4], bv[4];
+            for (int i = 0; i < 4; ++i) av[i] = As[qq][ty + 16 * i];
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[qq][tx + 16 * j];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + ty + 16 * i;
+        if (r >= nk) continue;
+        for (int j = 0; j < 4; ++j) {
+            const int x = c0 + tx + 16 * j;
+            if (x < nx) out[(long long)r * nx + x] = omega * (x_lo + x * hx) * acc[i][j];
+        }
+    }
+}
+
+// mode 0: dst = a + c b;  mode 1: dst = a + c (b + y)
+__global__ __launch_bounds__(256) void k_ho_combine(double* __restrict__ dst, const double* __restrict__ a,
+                                                   const double* __restrict__ b, const double* __restrict__ y,
+                                                   long long n, double c, int mode)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        dst[i] = mode == 0 ? fma(c, b[i], a[i]) : fma(c, b[i] + y[i], a[i]);
+}
+
+// Inverse of the (m+1) x (m+1) reduced patch matrix [4 2; 1 4 1; ...; 2 4] (the Hermite
+// rows of eq. 2.13 eliminated into the interpolation rows of eq. 2.12, times 6), by
+// Gauss-Jordan elimination (diagonally dominant: no pivoting needed).
+static std::vector<double> patch_inverse(int m)
+{
+    const int n = m + 1;
+    std::vector<double> A((size_t)n * n, 0.0), I((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        A[(size_t)i * n + i] = 4.0;
+        if (i > 0) A[(size_t)i * n + i - 1] = i == n - 1 ? 2.0 : 1.0;
+        if (i < n - 1) A[(size_t)i * n + i + 1] = i == 0 ? 2.0 : 1.0;
+        I[(size_t)i * n + i] = 1.0;
+    }
+    for (int k = 0; k < n; ++k) {
+        const double p = A[(size_t)k * n + k];
+        for (int j = 0; j < n; ++j) {
+            A[(size_t)k * n + j] /= p;
+            I[(size_t)k * n + j] /= p;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == k) continue;
+            const double f = A[(size_t)r * n + k];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                A[(size_t)r * n + j] -= f * A[(size_t)k * n + j];
+                I[(size_t)r * n + j] -= f * I[(size_t)k * n + j];
+            }
+        }
+    }
+    return I;
+}
+
+// Spectral differentiation on the periodic grid of n (even) points, spacing h:
+// D[p][q] = d(p - q), d(0) = 0, d(r) = (pi / (n h)) (-1)^r cot(pi r / n) -- the matrix of
+// F^-1 diag(i xi) F with the Nyquist mode's derivative set to zero.
+static std::vector<double> spectral_dk(int n, double h)
+{
+    std::vector<double> d(n, 0.0), D((size_t)n * n);
+    for (int r = 1; r < n; ++r) d[r] = (M_PI / (n * h)) * ((r % 2) ? -1.0 : 1.0) / std::tan(M_PI * r / n);
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q) D[(size_t)p * n + q] = d[((p - q) % n + n) % n];
+    return D;
+}
+
+}  // namespace chasm
+
+using namespace chasm;
+
+struct chasm_ho2d_s {
+    chasm_ho2d_desc desc;
+    hipStream_t stream = nullptr;
+    HoArgs args{};
+    void* tables = nullptr;
+    double* D = nullptr;
+    double *X = nullptr, *XA = nullptr, *Y = nullptr, *Z = nullptr;   // X, XA: two fields each
+    double* f = nullptr;
+    long long n = 0;
+    bool poisoned = false;
+};
+
+static chasm_status hfail(chasm_status st, const std::string& m)
+{
+    set_last_error(m);
+    return st;
+}
+
+extern "C" {
+
+chasm_status chasm_ho2d_create(const chasm_ho2d_desc* d, void* f_dev, void* hip_stream, chasm_ho2d_t* out)
+{
+    if (!out) return hfail(CHASM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d || !f_dev) return hfail(CHASM_EINVAL, "NULL argument");
+    if (d->nx < 2 || d->nx > 1024) return hfail(CHASM_EINVAL, "nx must be in 2..1024");
+    if (d->nk < 2 || d->nk > 4096 || d->nk % 2) return hfail(CHASM_EINVAL, "nk must be even, 2..4096");
+    if (!(d->hx > 0) || !(d->hk > 0) || !std::isfinite(d->x_lo) || !std::isfinite(d->k_lo) || !std::isfinite(d->hx) ||
+        !std::isfinite(d->hk))
+        return hfail(CHASM_EINVAL, "grid spacings must be finite and > 0");
+    if (d->patch < 2 || d->patch > d->nx - 1) return hfail(CHASM_EINVAL, "patch must be in 2..nx-1");
+    if (d->ghost < 1 || d->ghost > d->nx - 1) return hfail(CHASM_EINVAL, "ghost must be in 1..nx-1");
+    if (!std::isfinite(d->omega) || !(d->tau > 0) || !std::isfinite(d->tau))
+        return hfail(CHASM_EINVAL, "omega must be finite and tau finite and > 0");
+
+    AxisTables at;
+    std::string err;
+    if (!build_axis_tables(d->nx, d->patch, d->ghost, d->ghost, d->hx, 0, d->nk, d->k_lo, d->hk, d->tau, at, err))
+        return hfail(CHASM_EINVAL, err);
+    const int P = at.P, M = d->patch, mlast = at.MLAST;
+    if ((size_t)HO_LB * (2 * d->nx + 4 * P) * sizeof(double) > 65536)
+        return hfail(CHASM_EINVAL, "lines too long for the LDS line kernel (4 lines of 2 nx + 4 patches doubles <= 64 KiB)");
+    const std::vector<double> AM = patch_inverse(M), AL = patch_inverse(mlast), D = spectral_dk(d->nk, d->hk);
+
+    chasm_ho2d_s* h = new (std::nothrow) chasm_ho2d_s();
+    if (!h) return hfail(CHASM_ENOMEM, "host allocation failed");
+    h->desc = *d;
+    h->stream = (hipStream_t)hip_stream;
+    h->f = static_cast<double*>(f_dev);
+    h->n = (long long)d->nk * d->nx;
+    auto bail = [&](chasm_status s, const std::string& m) {
+        chasm_ho2d_destroy(h);
+        return hfail(s, m);
+    };
+    // one block: stencil | ainvM | ainvL | w (doubles), then shift (ints)
+    const size_t nd = at.stencil.size() + AM.size() + AL.size() + at.w.size();
+    std::vector<char> blob(nd * sizeof(double) + at.shift.size() * sizeof(int));
+    double* dp = reinterpret_cast<double*>(blob.data());
+    size_t o = 0;
+    const size_t o_st = o; std::copy(at.stencil.begin(), at.stencil.end(), dp + o); o += at.stencil.size();
+    const size_t o_am = o; std::copy(AM.begin(), AM.end(), dp + o); o += AM.size();
+    const size_t o_al = o; std::copy(AL.begin(), AL.end(), dp + o); o += AL.size();
+    const size_t o_w = o; std::copy(at.w.begin(), at.w.end(), dp + o); o += at.w.size();
+    std::copy(at.shift.begin(), at.shift.end(), reinterpret_cast<int*>(dp + o));
+    if (hipMalloc(&h->tables, blob.size()) != hipSuccess) return bail(CHASM_ENOMEM, "hipMalloc(tables) failed");
+    if (hipMalloc((void**)&h->D, D.size() * sizeof(double)) != hipSuccess) return bail(CHASM_ENOMEM, "hipMalloc(D) failed");
+    const size_t fb = (size_t)h->n * sizeof(double);
+    if (hipMalloc((void**)&h->X, 2 * fb) != hipSuccess || hipMalloc((void**)&h->XA, 2 * fb) != hipSuccess ||
+        hipMalloc((void**)&h->Y, fb) != hipSuccess || hipMalloc((void**)&h->Z, fb) != hipSuccess)
+        return bail(CHASM_ENOMEM, "hipMalloc(state) failed");
+    if (hipMemcpyAsync(h->tables, blob.data(), blob.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->D, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return bail(CHASM_EDEVICE, "table upload failed");
+    const double* tb = static_cast<const double*>(h->tables);
+    HoArgs& a = h->args;
+    a.N = d->nx;
+    a.M = M;
+    a.P = P;
+    a.mlast = mlast;
+    a.g = d->ghost;
+    a.nk = d->nk;
+    a.hx = d->hx;
+    a.stencil = tb + o_st;
+    a.ainvM = tb + o_am;
+    a.ainvL = tb + o_al;
+    a.w = tb + o_w;
+    a.shift = reinterpret_cast<const int*>(tb + o);
+    *out = h;
+    return CHASM_OK;
+}
+
+chasm_status chasm_ho2d_step(chasm_ho2d_t h, int32_t nsteps)
+{
+    if (!h) return hfail(CHASM_EINVAL, "handle is NULL");
+    if (h->poisoned) return hfail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
+    if (nsteps < 0) return hfail(CHASM_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return CHASM_OK;
+    const chasm_ho2d_desc& d = h->desc;
+    const HoArgs& a = h->args;
+    const long long n = h->n;
+    const size_t fb = (size_t)n * sizeof(double);
+    hipStream_t s = h->stream;
+    const int nlines = 2 * d.nk;
+    const size_t smem = (size_t)HO_LB * (2 * a.N + 4 * a.P) * sizeof(double);
+    const dim3 tgrid((unsigned)((d.nx + 63) / 64), (unsigned)((d.nk + 63) / 64));
+    const unsigned cgrid = (unsigned)std::min<long long>((n + 255) / 256, 4096);
+    double *F = h->X, *G = h->X + n, *FA = h->XA, *GA = h->XA + n;
+    hipError_t e = hipMemcpyAsync(F, h->f, fb, hipMemcpyDeviceToDevice, s);
+    for (int it = 0; it < nsteps && e == hipSuccess; ++it) {
+        hipLaunchKernelGGL(k_ho_theta, tgrid, dim3(256), 0, s, h->D, F, G, d.nk, d.nx, d.x_lo, d.hx, d.omega);
+        hipLaunchKernelGGL(k_ho_advect, dim3((unsigned)((nlines + HO_LB - 1) / HO_LB)), dim3(256), smem, s, h->X, h->XA,
+                           a, nlines);
+        hipLaunchKernelGGL(k_ho_combine, dim3(cgrid), dim3(256), 0, s, h->Y, FA, GA, (const double*)nullptr, n, d.tau, 0);
+        hipLaunchKernelGGL(k_ho_theta, tgrid, dim3(256), 0, s, h->D, h->Y, h->Z, d.nk, d.nx, d.x_lo, d.hx, d.omega);
+        hipLaunchKernelGGL(k_ho_combine, dim3(cgrid), dim3(256), 0, s, F, FA, GA, h->Z, n, 0.5 * d.tau, 1);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(h->f, F, fb, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+        h->poisoned = true;
+        return hfail(CHASM_EDEVICE, std::string("ho2d step: ") + hipGetErrorString(e));
+    }
+    return CHASM_OK;
+}
+
+chasm_status chasm_ho2d_destroy(chasm_ho2d_t h)
+{
+    if (!h) return CHASM_OK;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    hipFree(h->tables);
+    hipFree(h->D);
+    hipFree(h->X);
+    hipFree(h->XA);
+    hipFree(h->Y);
+    hipFree(h->Z);
+    delete h;
+    return CHASM_OK;
+}
+
+}  // extern "C"

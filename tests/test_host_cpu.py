@@ -28,13 +28,13 @@ def header_symbols():
 
 
 def test_library_exports_every_declared_symbol():
-    from paper_2205_02380_amd import lpc1, theta
+    from paper_2205_02380_amd import ho2d, lpc1, theta
     syms = header_symbols()
     assert len(syms) >= 16
     L = chasm.lib()
     for s in syms:
         assert hasattr(L, s), s
-    assert set(syms) == set(chasm.EXPORTS) | set(theta.EXPORTS) | set(lpc1.EXPORTS)
+    assert set(syms) == set(chasm.EXPORTS) | set(theta.EXPORTS) | set(lpc1.EXPORTS) | set(ho2d.EXPORTS)
     assert "gfx950" in chasm.chasm_advect_version()
 
 

@@ -10,8 +10,8 @@
 //                the Hermite ghosts, and the 4-tap evaluation by the owning patch
 //                (eqs. 3.7-3.8, Sec. 3.1.3), out of place.
 //   k_ho_theta   out[k][x] = omega x sum_q D[k][q] f[q][x]: a dense FP64 contraction
-//                with the circulant spectral differentiation matrix, 64 x 64 output
-//                tiles staged through LDS, 4 x 4 outputs per thread.
+//                with the circulant spectral differentiation matrix, 32 x 32 output
+//                tiles staged through LDS, 2 x 2 outputs per thread.
 //   k_ho_combine the predictor / corrector combinations.
 #include <hip/hip_runtime.h>
 
@@ -37,7 +37,7 @@ struct HoArgs {
     const double* w;           // nk x 4
 };
 
-constexpr int HO_LB = 4;       // lines per block
+constexpr int HO_LB = 8;       // lines per block
 
 __global__ __launch_bounds__(256) void k_ho_advect(const double* __restrict__ in, double* __restrict__ out, const HoArgs a,
                                                   int nlines)
@@ -68,23 +68,28 @@ __global__ __launch_bounds__(256) void k_ho_advect(const double* __restrict__ in
         dsl[e] = acc * a.hx;
     }
     __syncthreads();
+    // each thread takes one row i of one patch's inverse and applies it to the right-hand
+    // sides of all LB lines: rhs_jj = 6 phi_jj, plus 2 h d_L at jj = 0 and minus 2 h d_R at
+    // jj = m (added after the loop, the product being linear)
     const int per_line = N - 1 + P;                  // unknowns eta_0..eta_m of every patch
-    for (int e = tid; e < HO_LB * per_line; e += blockDim.x) {
-        const int ln = e / per_line, r = e % per_line;
+    for (int r = tid; r < per_line; r += blockDim.x) {
         const int l = min(r / (M + 1), P - 1);
         const int i = r - l * (M + 1);
         const int m = l < P - 1 ? M : a.mlast;
         const double* A = (l < P - 1 ? a.ainvM : a.ainvL) + (long long)i * (m + 1);
-        const double* ph = phi + ln * N + l * M;
-        const double dl = dsl[ln * (P + 1) + l], dr = dsl[ln * (P + 1) + l + 1];
-        double acc = 0.0;
+        double acc[HO_LB];
+#pragma unroll
+        for (int ln = 0; ln < HO_LB; ++ln) acc[ln] = 0.0;
         for (int jj = 0; jj <= m; ++jj) {
-            double rhs = 6.0 * ph[jj];
-            if (jj == 0) rhs += 2.0 * dl;
-            if (jj == m) rhs -= 2.0 * dr;
-            acc = fma(A[jj], rhs, acc);
+            const double aij = 6.0 * A[jj];
+#pragma unroll
+            for (int ln = 0; ln < HO_LB; ++ln) acc[ln] = fma(aij, phi[ln * N + l * M + jj], acc[ln]);
         }
-        eta[ln * ES + l * (M + 3) + 1 + i] = acc;
+        const double a0 = 2.0 * A[0], am = 2.0 * A[m];
+#pragma unroll
+        for (int ln = 0; ln < HO_LB; ++ln)
+            eta[ln * ES + l * (M + 3) + 1 + i] =
+                acc[ln] + a0 * dsl[ln * (P + 1) + l] - am * dsl[ln * (P + 1) + l + 1];
     }
     __syncthreads();
     for (int e = tid; e < HO_LB * P; e += blockDim.x) {
@@ -120,34 +125,37 @@ __global__ __launch_bounds__(256) void k_ho_theta(const double* __restrict__ D, 
                                                  double* __restrict__ out, int nk, int nx, double x_lo, double hx,
                                                  double omega)
 {
-    __shared__ double As[16][65];
-    __shared__ double Bs[16][64];
+    // 32 x 32 output tile per block (2 x 2 per thread), k-chunks of 32 through LDS
+    __shared__ double As[32][33];                       // As[q][r] = D[r0 + r][q0 + q]
+    __shared__ double Bs[32][33];                       // Bs[q][c] = f[q0 + q][c0 + c]
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-    double acc[4][4] = {};
-    for (int q0 = 0; q0 < nk; q0 += 16) {
-        for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-            const int rr = e / 16, qq = e % 16;                 // D[r0 + rr][q0 + qq]
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    double acc[2][2] = {};
+    for (int q0 = 0; q0 < nk; q0 += 32) {
+        for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+            const int rr = e / 32, qq = e % 32;
             const int r = r0 + rr, q = q0 + qq;
             As[qq][rr] = (r < nk && q < nk) ? D[(long long)r * nk + q] : 0.0;
-            const int qb = e / 64, cc = e % 64;                 // f[q0 + qb][c0 + cc]
+            const int qb = e / 32, cc = e % 32;
             const int qf = q0 + qb, x = c0 + cc;
             Bs[qb][cc] = (qf < nk && x < nx) ? f[(long long)qf * nx + x] : 0.0;
         }
         __syncthreads();
-        for (int qq = 0; qq < 16; ++qq) {
-            double av[4], bv[4];
-            for (int i = 0; i < 4; ++i) av[i] = As[qq][ty + 16 * i];
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[qq][tx + 16 * j];
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+#pragma unroll 8
+        for (int qq = 0; qq < 32; ++qq) {
+            const double a0 = As[qq][ty], a1 = As[qq][ty + 16];
+            const double b0 = Bs[qq][tx], b1 = Bs[qq][tx + 16];
+            acc[0][0] = fma(a0, b0, acc[0][0]);
+            acc[0][1] = fma(a0, b1, acc[0][1]);
+            acc[1][0] = fma(a1, b0, acc[1][0]);
+            acc[1][1] = fma(a1, b1, acc[1][1]);
         }
         __syncthreads();
     }
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 2; ++i) {
         const int r = r0 + ty + 16 * i;
         if (r >= nk) continue;
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
             const int x = c0 + tx + 16 * j;
             if (x < nx) out[(long long)r * nx + x] = omega * (x_lo + x * hx) * acc[i][j];
         }
@@ -252,7 +260,7 @@ chasm_status chasm_ho2d_create(const chasm_ho2d_desc* d, void* f_dev, void* hip_
         return hfail(CHASM_EINVAL, err);
     const int P = at.P, M = d->patch, mlast = at.MLAST;
     if ((size_t)HO_LB * (2 * d->nx + 4 * P) * sizeof(double) > 65536)
-        return hfail(CHASM_EINVAL, "lines too long for the LDS line kernel (4 lines of 2 nx + 4 patches doubles <= 64 KiB)");
+        return hfail(CHASM_EINVAL, "lines too long for the LDS line kernel (8 lines of 2 nx + 4 P doubles <= 64 KiB)");
     const std::vector<double> AM = patch_inverse(M), AL = patch_inverse(mlast), D = spectral_dk(d->nk, d->hk);
 
     chasm_ho2d_s* h = new (std::nothrow) chasm_ho2d_s();
@@ -316,7 +324,7 @@ chasm_status chasm_ho2d_step(chasm_ho2d_t h, int32_t nsteps)
     hipStream_t s = h->stream;
     const int nlines = 2 * d.nk;
     const size_t smem = (size_t)HO_LB * (2 * a.N + 4 * a.P) * sizeof(double);
-    const dim3 tgrid((unsigned)((d.nx + 63) / 64), (unsigned)((d.nk + 63) / 64));
+    const dim3 tgrid((unsigned)((d.nx + 31) / 32), (unsigned)((d.nk + 31) / 32));
     const unsigned cgrid = (unsigned)std::min<long long>((n + 255) / 256, 4096);
     double *F = h->X, *G = h->X + n, *FA = h->XA, *GA = h->XA + n;
     hipError_t e = hipMemcpyAsync(F, h->f, fb, hipMemcpyDeviceToDevice, s);

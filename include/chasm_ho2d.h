@@ -13,6 +13,11 @@
  * periodic k-grid (the circulant differentiation matrix, Nyquist mode set to zero).
  * Everything is FP64.
  *
+ * Inflow: the paper's run of this example to T = 10 (dx = 0.1, dk = 0.025, tau = 2e-5)
+ * is stable with zero inflow; evaluating inflow departure points from the ghost-extended
+ * spline lets a boundary mode grow from rounding (about e^4 per unit time at x = 12)
+ * and overtake the solution after t ~ 7 on that grid.
+ *
  * Field: f[k][x] (x fastest), nk * nx doubles of caller-owned device memory, advanced
  * in place.  x_i = x_lo + i hx (i < nx); k_i = k_lo + i hk (i < nk, nk even).
  * Status codes and chasm_advect_last_error() are shared with chasm_advect.h.
@@ -39,6 +44,9 @@ typedef struct {
     int32_t ghost;         /* PMBC stencil half-width g >= 1 */
     double omega;          /* V = omega x^2 / 2 */
     double tau;            /* time step */
+    int32_t inflow;        /* departure points outside [x_0, x_{nx-1}]: 0 give 0 (zero inflow),
+                              1 are evaluated by the outer patch with its ghost coefficients
+                              (the convention of chasm_advect.h) */
 } chasm_ho2d_desc;
 
 /* Validate (CHASM_EINVAL), build the FP64 tables on the host (PMBC stencils, patch

@@ -8,7 +8,8 @@ The Wigner equation with V = omega x^2 / 2 (m = hbar = 1) reads
 and is advanced by LPC1 (Sec. 2.2): the characteristic step in x of every k-line with
 the patched cubic spline of Sec. 3 (the C oracle's line routine, PMBC, natural closure),
 and Theta from the spectral derivative in k on the periodic k-grid (numpy's FFT as a
-library primitive; the Nyquist mode's derivative is set to zero).  The exact solution
+library primitive; the Nyquist mode's derivative is set to zero).  Departure points
+outside [x_0, x_{N-1}] give 0 (zero inflow) unless inflow="extrapolate".  The exact solution
 is f0 along the reverse-time Hamiltonian flow of eq. 5.2:
   X = cos(sqrt(w) t) x - sin(sqrt(w) t) k / sqrt(w),
   K = sqrt(w) sin(sqrt(w) t) x + cos(sqrt(w) t) k.
@@ -27,13 +28,21 @@ def axes(nx, x_lo, hx, nk, k_lo, hk):
     return x_lo + hx * np.arange(nx), k_lo + hk * np.arange(nk)
 
 
-def advect(f, x, k, hx, M, g, tau, stencil=None):
-    """One characteristic step of every k-line f[k][:] (shift alpha = k tau / hx)."""
+def advect(f, x, k, hx, M, g, tau, stencil=None, inflow="zero"):
+    """One characteristic step of every k-line f[k][:] (shift alpha = k tau / hx).
+    inflow "zero": nodes whose departure point x_j - alpha hx lies outside
+    [x_0, x_{N-1}] get 0; "extrapolate": the outer patch evaluates them with its ghost
+    coefficients (as on the 6-D path)."""
     N = f.shape[1]
     c = stencil if stencil is not None else oracle.stencils(N, M, g, hx)
     out = np.empty_like(f)
+    j = np.arange(N)
     for i, kv in enumerate(k):
-        out[i] = oracle.line(N, M, g, hx, kv * tau / hx, f[i], c=c)
+        a = kv * tau / hx
+        out[i] = oracle.line(N, M, g, hx, a, f[i], c=c)
+        if inflow == "zero":
+            t = j - a                               # departure point in units of hx from x_0
+            out[i][(t < 0) | (t > N - 1)] = 0.0
     return out
 
 
@@ -50,13 +59,13 @@ def theta(f, x, hk, omega):
     return omega * x[None, :] * dk_spectral(f, hk)
 
 
-def lpc1(f, x, k, hx, hk, M, g, omega, tau, nsteps):
+def lpc1(f, x, k, hx, hk, M, g, omega, tau, nsteps, inflow="zero"):
     c = oracle.stencils(f.shape[1], M, g, hx)
     f = np.asarray(f, dtype=np.float64)
     for _ in range(nsteps):
         th = theta(f, x, hk, omega)
-        af = advect(f, x, k, hx, M, g, tau, c)
-        ath = advect(th, x, k, hx, M, g, tau, c)
+        af = advect(f, x, k, hx, M, g, tau, c, inflow)
+        ath = advect(th, x, k, hx, M, g, tau, c, inflow)
         ft = af + tau * ath
         f = af + 0.5 * tau * theta(ft, x, hk, omega) + 0.5 * tau * ath
     return f

@@ -8,7 +8,8 @@
 //                reduced Hermite system solved as a product with its precomputed
 //                inverse (one output per thread, so a line's patches solve in parallel),
 //                the Hermite ghosts, and the 4-tap evaluation by the owning patch
-//                (eqs. 3.7-3.8, Sec. 3.1.3), out of place.
+//                (eqs. 3.7-3.8, Sec. 3.1.3), out of place; departure points outside
+//                the line give 0 unless the descriptor asks for ghost extrapolation.
 //   k_ho_theta   out[k][x] = omega x sum_q D[k][q] f[q][x]: a dense FP64 contraction
 //                with the circulant spectral differentiation matrix, 32 x 32 output
 //                tiles staged through LDS, 2 x 2 outputs per thread.
@@ -28,7 +29,7 @@ namespace chasm {
 void set_last_error(const std::string& msg);
 
 struct HoArgs {
-    int N, M, P, mlast, g, nk;
+    int N, M, P, mlast, g, nk, inflow;
     double hx;
     const double* stencil;     // (P+1) x (2g+1), slopes (not times h)
     const double* ainvM;       // (M+1)^2 inverse of [4 2; 1 4 1; ...; 2 4]
@@ -106,7 +107,10 @@ __global__ __launch_bounds__(256) void k_ho_advect(const double* __restrict__ in
         const int kk = L % a.nk;
         const int c = j + a.shift[kk];                           // departure cell
         double v = 0.0;
-        if (c >= -4 && c <= N + 2) {
+        // departure point inside [x_0, x_{N-1}]: cell 0 .. N-2, or exactly node N-1
+        // (beta = 0, i.e. w3 = beta^3/6 = 0)
+        const bool inside = c >= 0 && (c < N - 1 || (c == N - 1 && a.w[4 * kk + 3] == 0.0));
+        if ((inside || a.inflow == 1) && c >= -4 && c <= N + 2) {
             const int l = c < 0 ? 0 : min(c / M, P - 1);         // owner patch
             const int m = l < P - 1 ? M : a.mlast;
             const int nu = c - l * M;
@@ -253,6 +257,7 @@ chasm_status chasm_ho2d_create(const chasm_ho2d_desc* d, void* f_dev, void* hip_
     if (d->ghost < 1 || d->ghost > d->nx - 1) return hfail(CHASM_EINVAL, "ghost must be in 1..nx-1");
     if (!std::isfinite(d->omega) || !(d->tau > 0) || !std::isfinite(d->tau))
         return hfail(CHASM_EINVAL, "omega must be finite and tau finite and > 0");
+    if (d->inflow != 0 && d->inflow != 1) return hfail(CHASM_EINVAL, "inflow must be 0 or 1");
 
     AxisTables at;
     std::string err;
@@ -301,6 +306,7 @@ chasm_status chasm_ho2d_create(const chasm_ho2d_desc* d, void* f_dev, void* hip_
     a.mlast = mlast;
     a.g = d->ghost;
     a.nk = d->nk;
+    a.inflow = d->inflow;
     a.hx = d->hx;
     a.stencil = tb + o_st;
     a.ainvM = tb + o_am;

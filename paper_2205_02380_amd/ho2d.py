@@ -16,7 +16,7 @@ class chasm_ho2d_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("x_lo", ctypes.c_double), ("hx", ctypes.c_double),
                 ("nk", ctypes.c_int32), ("k_lo", ctypes.c_double), ("hk", ctypes.c_double),
                 ("patch", ctypes.c_int32), ("ghost", ctypes.c_int32),
-                ("omega", ctypes.c_double), ("tau", ctypes.c_double)]
+                ("omega", ctypes.c_double), ("tau", ctypes.c_double), ("inflow", ctypes.c_int32)]
 
 
 def lib():
@@ -38,9 +38,12 @@ def _check(st: int) -> None:
         raise chasm.ChasmError(st, chasm.chasm_advect_last_error())
 
 
-def make_desc(nx, x_lo, hx, nk, k_lo, hk, patch, ghost, omega, tau) -> chasm_ho2d_desc:
+INFLOW = {"zero": 0, "extrapolate": 1}
+
+
+def make_desc(nx, x_lo, hx, nk, k_lo, hk, patch, ghost, omega, tau, inflow: str = "zero") -> chasm_ho2d_desc:
     return chasm_ho2d_desc(int(nx), float(x_lo), float(hx), int(nk), float(k_lo), float(hk), int(patch), int(ghost),
-                           float(omega), float(tau))
+                           float(omega), float(tau), INFLOW[inflow])
 
 
 def chasm_ho2d_create(desc: chasm_ho2d_desc, f_dev: int, hip_stream: int) -> int:
@@ -61,14 +64,14 @@ def chasm_ho2d_destroy(h: Optional[int]) -> None:
 class HO2D:
     """Advance f[k][x] (contiguous float64 device tensor) in place."""
 
-    def __init__(self, f, nx, x_lo, hx, nk, k_lo, hk, patch, ghost, omega, tau, stream=None):
+    def __init__(self, f, nx, x_lo, hx, nk, k_lo, hk, patch, ghost, omega, tau, inflow: str = "zero", stream=None):
         import torch
         if not f.is_cuda or not f.is_contiguous() or f.dtype != torch.float64 or f.numel() != nx * nk:
             raise ValueError("f must be a contiguous float64 device tensor of nk x nx")
         self.f = f
         self.stream = stream if stream is not None else torch.cuda.current_stream(f.device)
-        self.h = chasm_ho2d_create(make_desc(nx, x_lo, hx, nk, k_lo, hk, patch, ghost, omega, tau), f.data_ptr(),
-                                   self.stream.cuda_stream)
+        self.h = chasm_ho2d_create(make_desc(nx, x_lo, hx, nk, k_lo, hk, patch, ghost, omega, tau, inflow),
+                                   f.data_ptr(), self.stream.cuda_stream)
 
     def step(self, n: int = 1) -> None:
         chasm_ho2d_step(self.h, n)

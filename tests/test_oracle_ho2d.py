@@ -48,3 +48,24 @@ def test_follows_the_exact_rotation_and_conserves_mass():
     assert e2 < 1e-5 and e2 < e1 / 8
     # the paper reports a mass loss of about 1e-13 with the natural condition and n_nb >= 20
     assert m1 < 1e-12 and m2 < 1e-12
+
+
+def test_inflow_modes_differ_only_at_inflow_nodes():
+    """Zero inflow sets exactly the nodes whose departure point leaves [x_0, x_{N-1}] to 0
+    (the right end for k < 0, the left end for k > 0); elsewhere it equals the
+    ghost-extrapolating step bitwise."""
+    x, k = ho2d.axes(41, -6.0, 0.3, 16, -3.2, 0.4)
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((16, 41))
+    tau = 0.05
+    z = ho2d.advect(f, x, k, 0.3, 10, 8, tau, inflow="zero")
+    e = ho2d.advect(f, x, k, 0.3, 10, 8, tau, inflow="extrapolate")
+    for i, kv in enumerate(k):
+        if kv < 0:
+            assert z[i, -1] == 0.0 and e[i, -1] != 0.0
+            assert np.array_equal(z[i, :-1], e[i, :-1])
+        elif kv > 0:
+            assert z[i, 0] == 0.0 and e[i, 0] != 0.0
+            assert np.array_equal(z[i, 1:], e[i, 1:])
+        else:
+            assert np.array_equal(z[i], e[i]) and np.allclose(z[i], f[i], rtol=0, atol=1e-13)

@@ -5,10 +5,14 @@ phase-space points), patches of 8 cells, ghost width 6, dt = 0.02, seeded 4-pack
 Gaussian mixture, FP32 storage and arithmetic.  A step is one pass of the whole hot
 path: the x1, x2 and x3 sweeps of every point.
 
-The field is resident in HBM before timing starts.  Each step is replayed as a HIP
-graph on the library's stream; a HIP event is recorded on that stream between steps,
-which gives the per-step latency distribution (p50/p99) and the mean duration of the
-dominant kernel (one kernel per step under the cube schedule).  Beside it: the plain
+The field is resident in HBM before timing starts.  Before the W warmup steps the GPU
+is brought to its steady clocks with about 0.4 s of plain device copies (an idle
+device runs its first tens of milliseconds of work up to 10 % slower).  The K timed
+steps are one library call (K graph replays back to back on the library's stream)
+between two HIP events; value, ms_per_step and the mean duration of the dominant
+kernel (one kernel per step under the cube schedule) come from that interval.  A
+separate latency pass of L steps, with a HIP event recorded after every step, gives
+the per-step latency distribution (p50/p99).  Beside it: the plain
 FP64 form (three launches per step, eager) and the FP64 CPU oracle timed on a bounded
 sample of k-points (cpu_baseline), whose result at those k-points also gives the
 error of the timed GPU run.
@@ -89,15 +93,43 @@ def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
     return gbs
 
 
+def settle(torch, dev, seconds=0.4, nbytes=1 << 28):
+    """Plain device copies for about `seconds`, so that the timed work starts at the
+    GPU's steady clocks.  Returns the number of copies."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        n += 20
+    del src, dst
+    return n
+
+
 def time_steps(adv, torch, steps, stream):
+    """Exactly `steps` steps as one library call between two events: seconds."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    adv.step(steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / 1e3
+
+
+def step_latencies(adv, torch, steps, stream):
+    """Latency pass: one step per call with an event after each; per-step ms."""
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
     ev[0].record(stream)
     for i in range(steps):
         adv.step(1)
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
-    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])     # ms
-    return ev[0].elapsed_time(ev[steps]) / 1e3, per
+    return np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
 
 
 METRIC = "6-D point-updates/s FP32 vs FP64 plain at <=1e-5 rel err; p50/p99 step latency"
@@ -146,25 +178,28 @@ def bench_large(args, name):
     kidx = inputs.k_sample(g, args.cpu_kpoints / g.nkpts, 40)
     start = np.stack([f[i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in kidx])
     steps = args.steps
+    lat = min(steps, args.latency_steps)
+    nall = args.warmup + steps + lat
     adv = chasm.Advect(f, g, w.patch, w.ghost, w.dt, schedule=sched, graph=True, reduce_each_step=True,
-                       history_cap=steps + args.warmup, stream=stream)
+                       history_cap=nall, stream=stream, out_of_place=True)
     sched = adv.schedule
+    settled = settle(torch, dev)
     adv.step(args.warmup)
-    torch.cuda.synchronize()
-    total_s, per = time_steps(adv, torch, steps, stream)
-    hist = adv.history(steps + args.warmup)
+    total_s = time_steps(adv, torch, steps, stream)
+    per = step_latencies(adv, torch, lat, stream)
+    hist = adv.history(nall)
     adv.close()
     got = np.stack([f[i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in kidx])
     del f
     torch.cuda.empty_cache()
     value = g.points * steps / total_s
     bpp = 8.0 if sched == "cube" else (16.0 if sched == "slab" else 24.0)
-    achieved = bpp * g.points / (float(per.mean()) / 1e3) / 1e9
+    achieved = bpp * g.points / (total_s / steps) / 1e9
     cpu = err = None
     if not args.no_cpu:
-        nst = min(args.warmup + steps, args.cpu_steps) if args.cpu_steps else args.warmup + steps
+        nst = min(nall, args.cpu_steps) if args.cpu_steps else nall
         cpu, ref = oracle_sample(g, w, start, kidx, nst)
-        if nst == args.warmup + steps:
+        if nst == nall:
             err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
     m0 = hist[0, 0, 0]
     return {
@@ -173,9 +208,11 @@ def bench_large(args, name):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded Gaussian-packet mixture, generated on the GPU)",
         "config": {"workload": f"{w.name}: {g.nx[0]}^3 x by {g.nk[0]}^3 k, {g.points} points, patch {w.patch[0]}, "
                                f"ghost {w.ghost}, dt {w.dt}, FP32, one job, FP64 mass/L2 every step",
-                   "schedule": sched, "graph": True},
+                   "schedule": sched, "graph": True, "out_of_place": True},
         "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
-                            "mean": float(per.mean())},
+                            "mean": float(per.mean()), "steps": lat,
+                            "pass": "separate, after the timed steps, one event per step"},
+        "settle_copies": settled, "steps_total": nall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": step_traffic(sched, name),
                      "kernel": "whole step (" + ("k_cube" if sched == "cube" else "k_slab + k_pencil") + ")",
@@ -235,6 +272,7 @@ def bench_theta(args):
     inputs.fill_separable(f, coef, gx, gk)
     out = torch.empty_like(f)
     th = theta.Theta(grid, [(0.0, 0.0, 0.0)], dtype="f32", stream=stream)
+    settle(torch, dev)
     for _ in range(args.warmup):
         th.apply(f, out)
     torch.cuda.synchronize()
@@ -295,6 +333,7 @@ def bench_lpc1(args):
     inputs.fill_separable(f, coef, gx, gk)
     tau = 0.025
     s = lpc1.LPC1(f, grid, 16, 8, tau, [(0.0, 0.0, 0.0)], stream=stream)
+    settle(torch, dev)
     s.step(args.warmup)
     torch.cuda.synchronize()
     steps = args.steps
@@ -403,6 +442,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--fp64-steps", type=int, default=20)
     ap.add_argument("--cpu-kpoints", type=int, default=24)
+    ap.add_argument("--latency-steps", type=int, default=50,
+                    help="steps of the separate per-step latency pass (at most --steps)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "serving", "theta", "lpc1", "ho2d"])
@@ -461,15 +502,18 @@ def main():
     torch.cuda.synchronize()
     adv = chasm.Advect(f, g, w.patch, w.ghost, w.dt, graph=True, stream=stream)
     sched = adv.schedule
+    lat = min(args.steps, args.latency_steps)
+    nall = args.warmup + args.steps + lat
+    settled = settle(torch, dev)
     adv.step(args.warmup)
-    torch.cuda.synchronize()
-    total_s, per = time_steps(adv, torch, args.steps, stream)
+    total_s = time_steps(adv, torch, args.steps, stream)
+    per = step_latencies(adv, torch, lat, stream)
     adv.close()
     value = points * args.steps / total_s
     ms_per_step = total_s * 1e3 / args.steps
     kernel = "k_cube" if sched == "cube" else "k_slab+k_pencil"
     bytes_alg = 8.0 * points                       # read + write of every FP32 value, once per launch
-    mean_kernel_s = float(per.mean()) / 1e3
+    mean_kernel_s = total_s / args.steps           # one launch per step, back to back
     achieved = bytes_alg / mean_kernel_s / 1e9
     gpu_cubes = np.stack([f[i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in kidx])
     del f
@@ -482,8 +526,7 @@ def main():
         inputs.fill_separable(f64, coef, gx, gk)
         adv64 = chasm.Advect(f64, g, w.patch, w.ghost, w.dt, schedule="plain", stream=stream)
         adv64.step(2)
-        torch.cuda.synchronize()
-        t64, per64 = time_steps(adv64, torch, args.fp64_steps, stream)
+        t64 = time_steps(adv64, torch, args.fp64_steps, stream)
         adv64.close()
         value64 = points * args.fp64_steps / t64
         del f64
@@ -493,7 +536,7 @@ def main():
     cpu = None
     err = None
     if not args.no_cpu:
-        cpu, ref = oracle_sample(g, w, start_cubes, kidx, args.warmup + args.steps)
+        cpu, ref = oracle_sample(g, w, start_cubes, kidx, nall)
         err = float(np.max(np.abs(gpu_cubes - ref)) / np.max(np.abs(ref)))
 
     traffic = measured_traffic(kernel, "C2")
@@ -513,7 +556,9 @@ def main():
         "config": {"workload": "32^3 x [-12,12)^3 by 16^3 k [-4,4)^3, 134217728 points, patch 8, ghost 6, "
                                "dt 0.02, FP32, one job", "schedule": sched, "graph": True},
         "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
-                            "mean": float(per.mean())},
+                            "mean": float(per.mean()), "steps": lat,
+                            "pass": "separate, after the timed steps, one event per step"},
+        "settle_copies": settled, "steps_total": nall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
                      "alg_bytes_per_launch": bytes_alg, "measured_copy_GBs": copy_gbs,

@@ -81,7 +81,16 @@ typedef enum {
 
 enum {
     CHASM_FLAG_REDUCE_EACH_STEP = 1u << 0,   /* record FP64 diagnostics after every step */
-    CHASM_FLAG_GRAPH = 1u << 1               /* replay each step as a captured HIP graph */
+    CHASM_FLAG_GRAPH = 1u << 1,              /* replay each step as a captured HIP graph */
+    /* Allocate a second field of the same shape and dtype (the stage field, one more
+     * field of device memory, owned by the handle) and run the sweeps out of place:
+     * SLAB and PLAIN read f in their first launch and write the stage field, and write
+     * f back in their last launch, so every step ends in f; CUBE runs the steps of one
+     * chasm_advect_step call in pairs (f -> stage -> f) and an odd last step in place.
+     * The arithmetic is unchanged (results are bitwise equal to in place); HBM serves a
+     * read stream and a write stream to different addresses faster than read-modify-
+     * write traffic on one buffer.  chasm_advect_step_many steps CUBE handles in place. */
+    CHASM_FLAG_OUT_OF_PLACE = 1u << 2
 };
 
 typedef struct {

@@ -24,7 +24,7 @@ CHASM_OK, CHASM_EINVAL, CHASM_ENOMEM, CHASM_EDEVICE, CHASM_ESTATE, CHASM_EUNSUPP
 CHASM_F32, CHASM_F64 = 0, 1
 CHASM_CLOSURE_PMBC, CHASM_CLOSURE_POLY3, CHASM_CLOSURE_NEUMANN = 0, 1, 2
 CHASM_SCHED_AUTO, CHASM_SCHED_CUBE, CHASM_SCHED_SLAB, CHASM_SCHED_PLAIN = 0, 1, 2, 3
-CHASM_FLAG_REDUCE_EACH_STEP, CHASM_FLAG_GRAPH = 1, 2
+CHASM_FLAG_REDUCE_EACH_STEP, CHASM_FLAG_GRAPH, CHASM_FLAG_OUT_OF_PLACE = 1, 2, 4
 
 SCHEDULES = {"auto": 0, "cube": 1, "slab": 2, "plain": 3}
 SCHEDULE_NAMES = {v: k for k, v in SCHEDULES.items()}
@@ -200,11 +200,12 @@ def chasm_advect_version() -> str:
 # ---- owning wrapper ------------------------------------------------------------
 class Advect:
     """A handle advancing ``f`` (a contiguous CUDA/HIP torch tensor of shape
-    [b][k3][k2][k1][x3][x2][x1] or without b) in place."""
+    [b][k3][k2][k1][x3][x2][x1] or without b); every step ends in ``f``.  With
+    ``out_of_place`` the sweeps go through a second, library-owned field."""
 
     def __init__(self, f, grid: Grid, patch, ghost: int, dt: float, closure: str = "pmbc",
                  schedule: str = "auto", reduce_each_step: bool = False, graph: bool = False,
-                 history_cap: int = 0, stream=None):
+                 history_cap: int = 0, stream=None, out_of_place: bool = False):
         import torch
         if not f.is_cuda or not f.is_contiguous():
             raise ValueError("f must be a contiguous device tensor")
@@ -215,7 +216,8 @@ class Advect:
         if f.numel() % cube:
             raise ValueError("f does not hold whole fields of this grid")
         nbatch = f.numel() // cube
-        flags = (CHASM_FLAG_REDUCE_EACH_STEP if reduce_each_step else 0) | (CHASM_FLAG_GRAPH if graph else 0)
+        flags = ((CHASM_FLAG_REDUCE_EACH_STEP if reduce_each_step else 0) | (CHASM_FLAG_GRAPH if graph else 0)
+                 | (CHASM_FLAG_OUT_OF_PLACE if out_of_place else 0))
         self.desc = make_desc(grid, patch, ghost, dt, dtype, closure, nbatch, flags, schedule, history_cap)
         self.f = f
         self.nbatch = nbatch

@@ -126,7 +126,9 @@ struct chasm_advect_s {
     int device = 0;
     const KernelSet* ks = nullptr;
     int schedule = CHASM_SCHED_AUTO;
-    Work work{};                     // one-job work list of this handle
+    Work work{};                     // one-job work list of this handle, in place (f -> f)
+    void* stage = nullptr;           // second field (CHASM_FLAG_OUT_OF_PLACE)
+    Work w_fs{}, w_sf{}, w_ss{};     // f -> stage, stage -> f, stage -> stage
     FinalizeArgs fin{};
     void* tables = nullptr;          // device block: FP64 tables then FP32 mirror, int shifts
     double* partials = nullptr;      // [rows][NRED]
@@ -140,6 +142,8 @@ struct chasm_advect_s {
     int hist_cap = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph2 = nullptr;     // two cube steps f -> stage -> f (CHASM_FLAG_OUT_OF_PLACE)
+    hipGraphExec_t gexec2 = nullptr;
     hipStream_t cap_stream = nullptr;
     bool poisoned = false;
 };
@@ -189,7 +193,8 @@ static chasm_status validate(const chasm_advect_desc* d, const KernelSet** ks_ou
     if (d->nbatch < 1) return fail(CHASM_EINVAL, "nbatch must be >= 1");
     if (d->schedule < CHASM_SCHED_AUTO || d->schedule > CHASM_SCHED_PLAIN) return fail(CHASM_EINVAL, "unknown schedule");
     if (d->history_cap < 0) return fail(CHASM_EINVAL, "history_cap must be >= 0");
-    if (d->flags & ~(uint32_t)(CHASM_FLAG_REDUCE_EACH_STEP | CHASM_FLAG_GRAPH)) return fail(CHASM_EINVAL, "unknown flags");
+    if (d->flags & ~(uint32_t)(CHASM_FLAG_REDUCE_EACH_STEP | CHASM_FLAG_GRAPH | CHASM_FLAG_OUT_OF_PLACE))
+        return fail(CHASM_EINVAL, "unknown flags");
     if (d->nx[0] != d->nx[1] || d->nx[0] != d->nx[2])
         return fail(CHASM_EUNSUPPORTED, "kernels are built for equal nx on the three axes");
     if (d->patch[0] != d->patch[1] || d->patch[0] != d->patch[2])
@@ -258,6 +263,12 @@ static bool build_tables(const chasm_advect_desc* d, const KernelSet* ks, TableB
     return true;
 }
 
+static size_t field_bytes(const chasm_advect_desc* d)
+{
+    const size_t pts = (size_t)d->nbatch * d->nk[0] * d->nk[1] * d->nk[2] * d->nx[0] * d->nx[1] * d->nx[2];
+    return pts * (d->dtype == CHASM_F64 ? sizeof(double) : sizeof(float));
+}
+
 static size_t workspace_bytes(const chasm_advect_desc* d, const KernelSet* ks, int sched, size_t table_bytes)
 {
     const long long nkp = (long long)d->nk[0] * d->nk[1] * d->nk[2];
@@ -268,28 +279,49 @@ static size_t workspace_bytes(const chasm_advect_desc* d, const KernelSet* ks, i
     b += (size_t)d->nbatch * FOLD_CHUNKS * NRED * sizeof(double) + 256;
     b += (size_t)d->nbatch * NRED * sizeof(double) + 256;
     if (d->flags & CHASM_FLAG_REDUCE_EACH_STEP) b += (size_t)cap * d->nbatch * NRED * sizeof(double) + 256 + 256;
+    if (d->flags & CHASM_FLAG_OUT_OF_PLACE) b += field_bytes(d) + 256;
     return b;
 }
 
-// Launch one step of schedule sched for the jobs of w on stream s.
-static hipError_t launch_step(const KernelSet* ks, int sched, const Work& w, double* part, hipStream_t s)
+// Launch one step of schedule sched on stream s; pw[p] is the work list of the step's
+// p-th launch (CUBE uses pw[0], SLAB pw[0..1], PLAIN pw[0..2]).
+static hipError_t launch_step(const KernelSet* ks, int sched, const Work* const pw[3], double* part, hipStream_t s)
 {
     hipError_t e = hipSuccess;
     switch (sched) {
     case CHASM_SCHED_CUBE:
-        e = ks->cube(w, part, s);
+        e = ks->cube(*pw[0], part, s);
         break;
     case CHASM_SCHED_SLAB:
-        e = ks->slab_x1x2(w, nullptr, s);
-        if (e == hipSuccess) e = ks->pencil_x3(w, part, s);
+        e = ks->slab_x1x2(*pw[0], nullptr, s);
+        if (e == hipSuccess) e = ks->pencil_x3(*pw[1], part, s);
         break;
     default:
-        e = ks->slab_x1(w, nullptr, s);
-        if (e == hipSuccess) e = ks->pencil_x2(w, nullptr, s);
-        if (e == hipSuccess) e = ks->pencil_x3(w, part, s);
+        e = ks->slab_x1(*pw[0], nullptr, s);
+        if (e == hipSuccess) e = ks->pencil_x2(*pw[1], nullptr, s);
+        if (e == hipSuccess) e = ks->pencil_x3(*pw[2], part, s);
         break;
     }
     return e;
+}
+
+// The work lists of one step of a handle.  In place, every launch reads and writes f.
+// Out of place, the first launch reads f and writes the stage field and the last one
+// reads the stage field and writes f (a middle PLAIN launch works on the stage field in
+// place), so a step still ends in f.  CUBE has a single launch per step: its
+// out-of-place form is the two-step pair of issue_cube_pair.
+static void step_passes(const chasm_advect_s* h, const Work* pw[3])
+{
+    if (!h->stage || h->schedule == CHASM_SCHED_CUBE) {
+        pw[0] = pw[1] = pw[2] = &h->work;
+    } else if (h->schedule == CHASM_SCHED_SLAB) {
+        pw[0] = &h->w_fs;
+        pw[1] = pw[2] = &h->w_sf;
+    } else {
+        pw[0] = &h->w_fs;
+        pw[1] = &h->w_ss;
+        pw[2] = &h->w_sf;
+    }
 }
 
 // Issue one step's kernels of one handle on stream s.
@@ -313,10 +345,28 @@ static hipError_t issue_step(chasm_advect_t h, hipStream_t s)
 {
     const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
     double* part = red ? h->partials : nullptr;
-    hipError_t e = launch_step(h->ks, h->schedule, h->work, part, s);
+    const Work* pw[3];
+    step_passes(h, pw);
+    hipError_t e = launch_step(h->ks, h->schedule, pw, part, s);
     if (e == hipSuccess && red) e = launch_finalize(h, h->partial_rows, true, s);
     return e;
 }
+
+// Two CUBE steps out of place: f -> stage, then stage -> f.
+static hipError_t issue_cube_pair(chasm_advect_t h, hipStream_t s)
+{
+    const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
+    double* part = red ? h->partials : nullptr;
+    const Work* first[3] = {&h->w_fs, &h->w_fs, &h->w_fs};
+    const Work* second[3] = {&h->w_sf, &h->w_sf, &h->w_sf};
+    hipError_t e = launch_step(h->ks, CHASM_SCHED_CUBE, first, part, s);
+    if (e == hipSuccess && red) e = launch_finalize(h, h->partial_rows, true, s);
+    if (e == hipSuccess) e = launch_step(h->ks, CHASM_SCHED_CUBE, second, part, s);
+    if (e == hipSuccess && red) e = launch_finalize(h, h->partial_rows, true, s);
+    return e;
+}
+
+static bool cube_pairs(const chasm_advect_s* h) { return h->stage && h->schedule == CHASM_SCHED_CUBE; }
 
 extern "C" {
 
@@ -400,6 +450,7 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
     h->work.first[0] = 0;
     h->work.first[1] = nkp * desc->nbatch;
     job.f = f_dev;
+    job.out = f_dev;
     job.nitems = nkp * desc->nbatch;
     for (int a = 0; a < 3; ++a) {
         job.nk[a] = desc->nk[a];
@@ -413,6 +464,15 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
     }
     h->fin.vol = h->fin.hx[0] * h->fin.hx[1] * h->fin.hx[2] * h->fin.hk[0] * h->fin.hk[1] * h->fin.hk[2];
 
+    if (desc->flags & CHASM_FLAG_OUT_OF_PLACE) {
+        if (hipMalloc(&h->stage, field_bytes(desc)) != hipSuccess)
+            return bail(CHASM_ENOMEM, "hipMalloc(stage field) failed");
+        h->w_fs = h->w_sf = h->w_ss = h->work;
+        h->w_fs.jobs[0].out = h->stage;
+        h->w_sf.jobs[0].f = h->stage;
+        h->w_ss.jobs[0].f = h->w_ss.jobs[0].out = h->stage;
+    }
+
     if (desc->flags & CHASM_FLAG_GRAPH) {
         if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
             return bail(CHASM_EDEVICE, "capture stream creation failed");
@@ -423,6 +483,15 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
         if (ce != hipSuccess || ee != hipSuccess) return bail(CHASM_EDEVICE, "step capture failed");
         if (hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0) != hipSuccess)
             return bail(CHASM_EDEVICE, "hipGraphInstantiate failed");
+        if (cube_pairs(h)) {
+            if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return bail(CHASM_EDEVICE, "hipStreamBeginCapture failed");
+            ce = issue_cube_pair(h, h->cap_stream);
+            ee = hipStreamEndCapture(h->cap_stream, &h->graph2);
+            if (ce != hipSuccess || ee != hipSuccess) return bail(CHASM_EDEVICE, "step-pair capture failed");
+            if (hipGraphInstantiate(&h->gexec2, h->graph2, nullptr, nullptr, 0) != hipSuccess)
+                return bail(CHASM_EDEVICE, "hipGraphInstantiate failed");
+        }
     }
     *out = h;
     return CHASM_OK;
@@ -433,7 +502,13 @@ chasm_status chasm_advect_step(chasm_advect_t h, int32_t nsteps)
     if (!h) return fail(CHASM_EINVAL, "handle is NULL");
     if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
     if (nsteps < 0) return fail(CHASM_EINVAL, "nsteps must be >= 0");
-    for (int32_t s = 0; s < nsteps; ++s) {
+    int32_t s = 0;
+    if (cube_pairs(h))
+        for (; s + 1 < nsteps; s += 2) {
+            hipError_t e = h->gexec2 ? hipGraphLaunch(h->gexec2, h->stream) : issue_cube_pair(h, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "step launch");
+        }
+    for (; s < nsteps; ++s) {
         hipError_t e = h->gexec ? hipGraphLaunch(h->gexec, h->stream) : issue_step(h, h->stream);
         if (e != hipSuccess) return hip_fail(h, e, "step launch");
     }
@@ -472,26 +547,33 @@ chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const i
                 done[a] = true;
                 continue;
             }
-            Work w{};
-            for (size_t b = a; b < live.size() && w.njobs < kMaxJobs; ++b) {
+            // One work list per launch of the step; job j of list p is pass p of its
+            // handle (in place, or through that handle's stage field).
+            Work w[3] = {};
+            for (size_t b = a; b < live.size() && w[0].njobs < kMaxJobs; ++b) {
                 chasm_advect_t o = live[b];
                 if (done[b] || o->ks != h->ks || o->schedule != h->schedule ||
                     (o->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP))
                     continue;
                 const long long items = o->work.jobs[0].nitems;
-                if (w.first[w.njobs] + items > (1LL << 24)) break;   // keep launch grids small
-                w.jobs[w.njobs] = o->work.jobs[0];
-                w.first[w.njobs + 1] = w.first[w.njobs] + items;
-                ++w.njobs;
+                if (w[0].first[w[0].njobs] + items > (1LL << 24)) break;   // keep launch grids small
+                const Work* pw[3];
+                step_passes(o, pw);
+                for (int p = 0; p < 3; ++p) {
+                    w[p].jobs[w[p].njobs] = pw[p]->jobs[0];
+                    w[p].first[w[p].njobs + 1] = w[p].first[w[p].njobs] + items;
+                    ++w[p].njobs;
+                }
                 done[b] = true;
             }
-            if (w.njobs == 0) {   // a single job larger than the per-launch bound
+            if (w[0].njobs == 0) {   // a single job larger than the per-launch bound
                 hipError_t e = issue_step(h, s);
                 if (e != hipSuccess) return hip_fail(h, e, "step launch");
                 done[a] = true;
                 continue;
             }
-            hipError_t e = launch_step(h->ks, h->schedule, w, nullptr, s);
+            const Work* pw[3] = {&w[0], &w[1], &w[2]};
+            hipError_t e = launch_step(h->ks, h->schedule, pw, nullptr, s);
             if (e != hipSuccess) return hip_fail(h, e, "batched step launch");
         }
     }
@@ -605,6 +687,9 @@ chasm_status chasm_advect_destroy(chasm_advect_t h)
     if (h->stream || h->tables) e = hipStreamSynchronize(h->stream);
     if (h->gexec) hipGraphExecDestroy(h->gexec);
     if (h->graph) hipGraphDestroy(h->graph);
+    if (h->gexec2) hipGraphExecDestroy(h->gexec2);
+    if (h->graph2) hipGraphDestroy(h->graph2);
+    if (h->stage) hipFree(h->stage);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->tables) hipFree(h->tables);
     if (h->partials) hipFree(h->partials);

@@ -6,7 +6,9 @@
 // (eqs. 3.11-3.12 factored axis by axis, order x1, x2, x3) are independent per item,
 // because the shift alpha_d = k_d dt / h_d depends on k only.
 //
-// Kernels (each reads and writes f once per launch, in place):
+// Kernels (each reads the job's field f and writes its destination `out` once per
+// launch; out == f is in place, out != f runs the pass out of place into a buffer of
+// the same shape):
 //   k_cube    all three sweeps of one item with the whole x-cube in LDS
 //             (N^2 (N+1) values, rows padded to N+1 so x1-, x2- and x3-lines are
 //             bank-conflict free): 8 B/point-update in FP32.
@@ -32,7 +34,8 @@ struct AxisTabDev {
 };
 
 struct JobDev {
-    void* f;               // field base (caller-owned device memory)
+    void* f;               // field base the pass reads
+    void* out;             // base the pass writes: f (in place) or a field of the same shape
     long long nitems;      // nbatch * nk1 * nk2 * nk3
     int nk[3];
     AxisTabDev ax[3];
@@ -377,7 +380,7 @@ __global__ __launch_bounds__(NT) void k_cube(const Work w, double* __restrict__ 
         }
         __syncthreads();
         if (next < total) fill(0);
-        const Buf b(static_cast<T*>(job.f) + local * (long long)(N * N * N), CUBE_BYTES);
+        const Buf b(static_cast<T*>(job.out) + local * (long long)(N * N * N), CUBE_BYTES);
         static_for<0, NV / NT>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             b.template store16<T>(out[q], tid * 16u, (uint32_t)(q * NT * 16));
@@ -406,9 +409,11 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
     const int slab0 = (blockIdx.x % BPI) * S;
     int ik[3];
     item_k(job, item, ik);
-    T* __restrict__ base_ptr = static_cast<T*>(job.f) + item * (long long)(N * N * N) + (long long)slab0 * N * N;
+    const long long off = item * (long long)(N * N * N) + (long long)slab0 * N * N;
+    const T* in_ptr = static_cast<const T*>(job.f) + off;
+    T* out_ptr = static_cast<T*>(job.out) + off;
 
-    const V* __restrict__ src = reinterpret_cast<const V*>(base_ptr);
+    const V* src = reinterpret_cast<const V*>(in_ptr);
 #pragma unroll
     for (int e = threadIdx.x; e < S * N * N / VW; e += NT) {
         const V x = src[e];
@@ -432,7 +437,7 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
     __syncthreads();
 
     if (!X2) {
-        V* __restrict__ dst = reinterpret_cast<V*>(base_ptr);
+        V* dst = reinterpret_cast<V*>(out_ptr);
 #pragma unroll
         for (int e = threadIdx.x; e < S * N * N / VW; e += NT) {
             const int row = (e * VW) / N, x1 = (e * VW) % N;
@@ -446,7 +451,7 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
         const auto kc = axis_coef<T>(job, 1, ik[1], sigma);
         const int slab = threadIdx.x / N, col = threadIdx.x % N;
         const int base = slab * N * PX + col;
-        T* __restrict__ out = base_ptr + slab * N * N + col;
+        T* out = out_ptr + slab * N * N + col;
         dispatch_sigma(sigma, [&](auto sc) {
             T v[N];
 #pragma unroll
@@ -469,7 +474,7 @@ __global__ __launch_bounds__(NT) void k_pencil(const Work w, double* __restrict_
     const int L = (blockIdx.x % BPI) * NT + threadIdx.x;
     int ik[3];
     item_k(job, item, ik);
-    T* __restrict__ cube = static_cast<T*>(job.f) + item * (long long)(N * N * N);
+    const long long off = item * (long long)(N * N * N);
 
     // o1, o2: indices of the two other axes (x1 and x2 for AXIS 2, x1 and x3 for AXIS 1)
     const int o1 = L % N, o2 = L / N;
@@ -477,7 +482,8 @@ __global__ __launch_bounds__(NT) void k_pencil(const Work w, double* __restrict_
 
     int sigma;
     const auto kc = axis_coef<T>(job, AXIS, ik[AXIS], sigma);
-    const Buf buf(cube, (uint32_t)(N * N * N * sizeof(T)));
+    const Buf buf(static_cast<const T*>(job.f) + off, (uint32_t)(N * N * N * sizeof(T)));
+    const Buf obuf(static_cast<T*>(job.out) + off, (uint32_t)(N * N * N * sizeof(T)));
     const uint32_t voff = (uint32_t)base * sizeof(T);
     constexpr uint32_t sstride = (uint32_t)((AXIS == 2 ? N * N : N) * sizeof(T));
     T v[N];
@@ -489,10 +495,10 @@ __global__ __launch_bounds__(NT) void k_pencil(const Work w, double* __restrict_
     dispatch_sigma(sigma, [&](auto sc) {
         constexpr int SIG = decltype(sc)::value;
         if constexpr (!RED) {
-            advect_line<T, N, M, G, CL, SIG>(v, kc, sigma, [&](int j, T x) { buf.store<T>(x, voff, j * sstride); });
+            advect_line<T, N, M, G, CL, SIG>(v, kc, sigma, [&](int j, T x) { obuf.store<T>(x, voff, j * sstride); });
         } else {
             advect_line<T, N, M, G, CL, SIG>(v, kc, sigma, [&](int j, T x) {
-                buf.store<T>(x, voff, j * sstride);
+                obuf.store<T>(x, voff, j * sstride);
                 const double y = (double)x;
                 s += y;
                 s2 = fma(y, y, s2);

@@ -81,6 +81,15 @@ def test_cube_schedule_rejected_when_cube_exceeds_lds():
     assert 0 < chasm.chasm_advect_workspace_bytes(d) < 64 << 20
 
 
+def test_out_of_place_workspace_adds_one_field():
+    for name, dtype, size in (("C2", "f32", 4), ("C1", "f64", 8)):
+        w = inputs.workload(name)
+        d = chasm.make_desc(w.grid, w.patch, w.ghost, w.dt, dtype)
+        base = chasm.chasm_advect_workspace_bytes(d)
+        d.flags = chasm.CHASM_FLAG_OUT_OF_PLACE
+        assert chasm.chasm_advect_workspace_bytes(d) - base == w.grid.points * size + 256
+
+
 def test_null_arguments_fail_without_device():
     L = chasm.lib()
     assert L.chasm_advect_create(None, None, None, None) == chasm.CHASM_EINVAL

@@ -10,8 +10,9 @@
  * f(x, k) by LPC1 (Sec. 2.2): the characteristic step in x of every k-line with the
  * patched cubic spline of Sec. 3 (PMBC, natural closure, patches of `patch` cells,
  * stencil half-width `ghost`), and Theta from the spectral derivative in k on the
- * periodic k-grid (the circulant differentiation matrix, Nyquist mode set to zero).
- * Everything is FP64.
+ * periodic k-grid (F^-1 diag(i xi) F, Nyquist mode set to zero): by FFT when nk is a
+ * power of two in 64..1024, else as the product with the circulant differentiation
+ * matrix.  Everything is FP64.
  *
  * Inflow: the paper's run of this example to T = 10 (dx = 0.1, dk = 0.025, tau = 2e-5)
  * is stable with zero inflow; evaluating inflow departure points from the ghost-extended

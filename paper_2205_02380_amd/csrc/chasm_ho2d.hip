@@ -10,10 +10,18 @@
 //                the Hermite ghosts, and the 4-tap evaluation by the owning patch
 //                (eqs. 3.7-3.8, Sec. 3.1.3), out of place; departure points outside
 //                the line give 0 unless the descriptor asks for ghost extrapolation.
-//   k_ho_theta   out[k][x] = omega x sum_q D[k][q] f[q][x]: a dense FP64 contraction
-//                with the circulant spectral differentiation matrix, 32 x 32 output
-//                tiles staged through LDS, 2 x 2 outputs per thread.
-//   k_ho_combine the predictor / corrector combinations.
+//   k_ho_dk      Theta by transforms, for nk = L1 L2 a power of two in 64..1024: two
+//                real k-lines (x columns 2c, 2c+1) form one complex line, since the
+//                derivative F^-1 diag(i xi) F maps real lines to real lines; a
+//                four-step transform (L1-point register transforms over stride-L2
+//                elements, twiddles, L2-point register transforms), the multiply by
+//                i xi / nk (Nyquist mode 0) and the inverse in reverse order, with two
+//                LDS transposes per line.  Mode 1 fuses the LPC1 corrector: it reads
+//                FA, GA, transforms Y = FA + tau GA and writes FA + tau/2 (GA + Theta Y).
+//   k_ho_theta   any other even nk: out[k][x] = omega x sum_q D[k][q] f[q][x], a dense
+//                FP64 contraction with the circulant spectral differentiation matrix,
+//                32 x 32 output tiles staged through LDS, 2 x 2 outputs per thread.
+//   k_ho_combine the predictor / corrector combinations of the dense path.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,6 +31,7 @@
 #include <vector>
 
 #include "../../include/chasm_ho2d.h"
+#include "chasm_fft.hpp"
 #include "chasm_tables.hpp"
 
 namespace chasm {
@@ -166,6 +175,107 @@ __global__ __launch_bounds__(256) void k_ho_theta(const double* __restrict__ D, 
     }
 }
 
+struct DkArgs {
+    int nx;
+    double x_lo, hx, hk, omega, tau;
+};
+
+// Complex lines per block and threads per block of k_ho_dk (one wave).
+template <int L1, int L2>
+struct DkShape {
+    static constexpr int L = L1 * L2;
+    static constexpr int TL = L2 > L1 ? L2 : L1;     // threads per complex line
+    static constexpr int CLB = 64 / TL;              // complex lines per block
+    static constexpr int NT = CLB * TL;
+    static constexpr int RS = L2 + 1;                // LDS row of [k1][n2], padded
+};
+
+// MODE 0: out = omega x d_k a.  MODE 1: y = a + tau b, out = a + tau/2 (b + omega x d_k y).
+// tw[j] = e^{+2 pi i j / L}.  Index convention of the four-step transform: element
+// n = L2 n1 + n2, frequency m = k1 + L1 k2.  Each lane reads and writes its own
+// elements in HBM (one wave per block, so the block count, not the run length of a
+// row, sets how much of the chip takes part: staging a 16-column tile through LDS
+// for row-contiguous accesses ran 2.3x slower at nx = 241, nk = 512).
+template <int L1, int L2, int MODE>
+__global__ __launch_bounds__(64) void k_ho_dk(const double* __restrict__ a, const double* __restrict__ b,
+                                              double* __restrict__ out, const fft::cd* __restrict__ tw,
+                                              const DkArgs p)
+{
+    using namespace fft;
+    using S = DkShape<L1, L2>;
+    static_assert(S::NT == 64, "one wave per block");
+    constexpr int L = S::L;
+    __shared__ cd lds[S::CLB * L1 * S::RS];
+    const int lt = threadIdx.x % S::TL, cl = threadIdx.x / S::TL;
+    const int xa = 2 * (blockIdx.x * S::CLB + cl), xb = xa + 1;
+    const bool has_a = xa < p.nx, has_b = xb < p.nx;
+    cd* Y = lds + cl * L1 * S::RS;
+    auto input = [&](long long i) { return MODE == 0 ? a[i] : fma(p.tau, b[i], a[i]); };
+
+    // Step 1 (thread n2 = lt): L1-point transforms over n1, twiddle e^{-2 pi i n2 k1 / L}.
+    if (lt < L2 && has_a) {
+        const int n2 = lt;
+        cd v[L1];
+        sfor<0, L1>([&](auto ic) {
+            constexpr int n1 = decltype(ic)::value;
+            const long long row = (long long)(L2 * n1 + n2) * p.nx;
+            v[n1] = {input(row + xa), has_b ? input(row + xb) : 0.0};
+        });
+        transform<L1, -1>(v);
+        sfor<0, L1>([&](auto kc) {
+            constexpr int k1 = decltype(kc)::value;
+            cd w = v[k1];
+            if constexpr (k1 > 0) w = cmul(w, conj(tw[(n2 * k1) & (L - 1)]));
+            Y[k1 * S::RS + n2] = w;
+        });
+    }
+    __syncthreads();
+    // Step 2 (thread k1 = lt): L2-point transforms over n2 give X[k1 + L1 k2]; multiply by
+    // i xi_m / L; inverse L2-point transforms; twiddle e^{+2 pi i n2 k1 / L}.
+    if (lt < L1 && has_a) {
+        const int k1 = lt;
+        cd v[L2];
+        sfor<0, L2>([&](auto ic) { v[decltype(ic)::value] = Y[k1 * S::RS + decltype(ic)::value]; });
+        transform<L2, -1>(v);
+        const double unit = 2.0 * kPi / (L * p.hk) / L;
+        sfor<0, L2>([&](auto kc) {
+            constexpr int k2 = decltype(kc)::value;
+            const int m = k1 + L1 * k2;
+            const double xi = m < L / 2 ? (double)m * unit : (m == L / 2 ? 0.0 : (double)(m - L) * unit);
+            v[k2] = {-xi * v[k2].im, xi * v[k2].re};
+        });
+        transform<L2, +1>(v);
+        sfor<0, L2>([&](auto nc) {
+            constexpr int n2 = decltype(nc)::value;
+            cd w = v[n2];
+            if constexpr (n2 > 0) w = cmul(w, tw[(n2 * k1) & (L - 1)]);
+            Y[k1 * S::RS + n2] = w;
+        });
+    }
+    __syncthreads();
+    // Step 3 (thread n2 = lt): inverse L1-point transforms over k1 give d_k y at rows
+    // L2 n1 + n2; real part column xa, imaginary part column xb.
+    if (lt < L2 && has_a) {
+        const int n2 = lt;
+        cd v[L1];
+        sfor<0, L1>([&](auto kc) { v[decltype(kc)::value] = Y[decltype(kc)::value * S::RS + n2]; });
+        transform<L1, +1>(v);
+        const double fa = p.omega * (p.x_lo + xa * p.hx), fb = p.omega * (p.x_lo + xb * p.hx);
+        sfor<0, L1>([&](auto ic) {
+            constexpr int n1 = decltype(ic)::value;
+            const long long row = (long long)(L2 * n1 + n2) * p.nx;
+            if constexpr (MODE == 0) {
+                out[row + xa] = fa * v[n1].re;
+                if (has_b) out[row + xb] = fb * v[n1].im;
+            } else {
+                const double h = 0.5 * p.tau;
+                out[row + xa] = fma(h, b[row + xa] + fa * v[n1].re, a[row + xa]);
+                if (has_b) out[row + xb] = fma(h, b[row + xb] + fb * v[n1].im, a[row + xb]);
+            }
+        });
+    }
+}
+
 // mode 0: dst = a + c b;  mode 1: dst = a + c (b + y)
 __global__ __launch_bounds__(256) void k_ho_combine(double* __restrict__ dst, const double* __restrict__ a,
                                                    const double* __restrict__ b, const double* __restrict__ y,
@@ -228,7 +338,8 @@ struct chasm_ho2d_s {
     hipStream_t stream = nullptr;
     HoArgs args{};
     void* tables = nullptr;
-    double* D = nullptr;
+    double* D = nullptr;             // dense path: the differentiation matrix
+    fft::cd* tw = nullptr;           // transform path: e^{+2 pi i j / nk}, j < nk
     double *X = nullptr, *XA = nullptr, *Y = nullptr, *Z = nullptr;   // X, XA: two fields each
     double* f = nullptr;
     long long n = 0;
@@ -239,6 +350,34 @@ static chasm_status hfail(chasm_status st, const std::string& m)
 {
     set_last_error(m);
     return st;
+}
+
+// Transform path for nk in {64, ..., 1024}: nk = L1 L2.
+static bool dk_by_transform(int nk) { return nk >= 64 && nk <= 1024 && (nk & (nk - 1)) == 0; }
+
+template <int L1, int L2>
+static void launch_dk_t(int mode, const double* a, const double* b, double* out, const fft::cd* tw, const DkArgs& p,
+                        hipStream_t s)
+{
+    using S = DkShape<L1, L2>;
+    const int ncl = (p.nx + 1) / 2;
+    const dim3 grid((unsigned)((ncl + S::CLB - 1) / S::CLB));
+    if (mode == 0)
+        hipLaunchKernelGGL((k_ho_dk<L1, L2, 0>), grid, dim3(S::NT), 0, s, a, b, out, tw, p);
+    else
+        hipLaunchKernelGGL((k_ho_dk<L1, L2, 1>), grid, dim3(S::NT), 0, s, a, b, out, tw, p);
+}
+
+static void launch_dk(int nk, int mode, const double* a, const double* b, double* out, const fft::cd* tw,
+                      const DkArgs& p, hipStream_t s)
+{
+    switch (nk) {
+    case 64: launch_dk_t<8, 8>(mode, a, b, out, tw, p, s); break;
+    case 128: launch_dk_t<8, 16>(mode, a, b, out, tw, p, s); break;
+    case 256: launch_dk_t<16, 16>(mode, a, b, out, tw, p, s); break;
+    case 512: launch_dk_t<16, 32>(mode, a, b, out, tw, p, s); break;
+    default: launch_dk_t<32, 32>(mode, a, b, out, tw, p, s); break;
+    }
 }
 
 extern "C" {
@@ -266,7 +405,12 @@ chasm_status chasm_ho2d_create(const chasm_ho2d_desc* d, void* f_dev, void* hip_
     const int P = at.P, M = d->patch, mlast = at.MLAST;
     if ((size_t)HO_LB * (2 * d->nx + 4 * P) * sizeof(double) > 65536)
         return hfail(CHASM_EINVAL, "lines too long for the LDS line kernel (8 lines of 2 nx + 4 P doubles <= 64 KiB)");
-    const std::vector<double> AM = patch_inverse(M), AL = patch_inverse(mlast), D = spectral_dk(d->nk, d->hk);
+    const bool by_transform = dk_by_transform(d->nk);
+    const std::vector<double> AM = patch_inverse(M), AL = patch_inverse(mlast);
+    const std::vector<double> D = by_transform ? std::vector<double>() : spectral_dk(d->nk, d->hk);
+    std::vector<fft::cd> TW;
+    if (by_transform)
+        for (int j = 0; j < d->nk; ++j) TW.push_back(fft::twiddle(j, d->nk, +1));
 
     chasm_ho2d_s* h = new (std::nothrow) chasm_ho2d_s();
     if (!h) return hfail(CHASM_ENOMEM, "host allocation failed");
@@ -289,13 +433,19 @@ chasm_status chasm_ho2d_create(const chasm_ho2d_desc* d, void* f_dev, void* hip_
     const size_t o_w = o; std::copy(at.w.begin(), at.w.end(), dp + o); o += at.w.size();
     std::copy(at.shift.begin(), at.shift.end(), reinterpret_cast<int*>(dp + o));
     if (hipMalloc(&h->tables, blob.size()) != hipSuccess) return bail(CHASM_ENOMEM, "hipMalloc(tables) failed");
-    if (hipMalloc((void**)&h->D, D.size() * sizeof(double)) != hipSuccess) return bail(CHASM_ENOMEM, "hipMalloc(D) failed");
+    if (!by_transform && hipMalloc((void**)&h->D, D.size() * sizeof(double)) != hipSuccess)
+        return bail(CHASM_ENOMEM, "hipMalloc(D) failed");
+    if (by_transform && hipMalloc((void**)&h->tw, TW.size() * sizeof(fft::cd)) != hipSuccess)
+        return bail(CHASM_ENOMEM, "hipMalloc(twiddles) failed");
     const size_t fb = (size_t)h->n * sizeof(double);
     if (hipMalloc((void**)&h->X, 2 * fb) != hipSuccess || hipMalloc((void**)&h->XA, 2 * fb) != hipSuccess ||
         hipMalloc((void**)&h->Y, fb) != hipSuccess || hipMalloc((void**)&h->Z, fb) != hipSuccess)
         return bail(CHASM_ENOMEM, "hipMalloc(state) failed");
     if (hipMemcpyAsync(h->tables, blob.data(), blob.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
-        hipMemcpyAsync(h->D, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+        (h->D && hipMemcpyAsync(h->D, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
+                     hipSuccess) ||
+        (h->tw && hipMemcpyAsync(h->tw, TW.data(), TW.size() * sizeof(fft::cd), hipMemcpyHostToDevice, h->stream) !=
+                      hipSuccess) ||
         hipStreamSynchronize(h->stream) != hipSuccess)
         return bail(CHASM_EDEVICE, "table upload failed");
     const double* tb = static_cast<const double*>(h->tables);
@@ -334,7 +484,16 @@ chasm_status chasm_ho2d_step(chasm_ho2d_t h, int32_t nsteps)
     const unsigned cgrid = (unsigned)std::min<long long>((n + 255) / 256, 4096);
     double *F = h->X, *G = h->X + n, *FA = h->XA, *GA = h->XA + n;
     hipError_t e = hipMemcpyAsync(F, h->f, fb, hipMemcpyDeviceToDevice, s);
-    for (int it = 0; it < nsteps && e == hipSuccess; ++it) {
+    const DkArgs dp{d.nx, d.x_lo, d.hx, d.hk, d.omega, d.tau};
+    for (int it = 0; it < nsteps && e == hipSuccess && h->tw; ++it) {
+        // predictor Theta F; advect (F, Theta F); corrector fused with Theta (FA + tau GA)
+        launch_dk(d.nk, 0, F, nullptr, G, h->tw, dp, s);
+        hipLaunchKernelGGL(k_ho_advect, dim3((unsigned)((nlines + HO_LB - 1) / HO_LB)), dim3(256), smem, s, h->X, h->XA,
+                           a, nlines);
+        launch_dk(d.nk, 1, FA, GA, F, h->tw, dp, s);
+        e = hipGetLastError();
+    }
+    for (int it = 0; it < nsteps && e == hipSuccess && !h->tw; ++it) {
         hipLaunchKernelGGL(k_ho_theta, tgrid, dim3(256), 0, s, h->D, F, G, d.nk, d.nx, d.x_lo, d.hx, d.omega);
         hipLaunchKernelGGL(k_ho_advect, dim3((unsigned)((nlines + HO_LB - 1) / HO_LB)), dim3(256), smem, s, h->X, h->XA,
                            a, nlines);
@@ -354,13 +513,9 @@ chasm_status chasm_ho2d_step(chasm_ho2d_t h, int32_t nsteps)
 chasm_status chasm_ho2d_destroy(chasm_ho2d_t h)
 {
     if (!h) return CHASM_OK;
-    if (h->stream) hipStreamSynchronize(h->stream);
-    hipFree(h->tables);
-    hipFree(h->D);
-    hipFree(h->X);
-    hipFree(h->XA);
-    hipFree(h->Y);
-    hipFree(h->Z);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void* p : {(void*)h->tables, (void*)h->D, (void*)h->tw, (void*)h->X, (void*)h->XA, (void*)h->Y, (void*)h->Z})
+        if (p) (void)hipFree(p);
     delete h;
     return CHASM_OK;
 }

@@ -30,6 +30,10 @@ def run(nx, hx, nk, hk, M, g, tau, steps, inflow="zero"):
     (121, 0.2, 128, 0.1, 30, 20, 0.005, 10),
     (241, 0.1, 512, 0.025, 60, 20, 0.00002, 5),         # the paper's grid and time step
     (61, 0.4, 64, 0.2, 16, 6, 0.01, 8),                   # ragged last patch (60 = 3 x 16 + 12)
+    (121, 0.2, 256, 0.05, 30, 20, 0.004, 6),              # transform path 16 x 16
+    (121, 0.2, 1024, 0.0125, 30, 20, 0.002, 4),           # transform path 32 x 32
+    (81, 0.3, 96, 0.1, 20, 10, 0.005, 6),                 # nk not a power of two: dense path
+    (41, 0.6, 2048, 0.00625, 10, 6, 0.001, 3),            # nk above the transform sizes: dense path
 ])
 def test_ho2d_matches_oracle(nx, hx, nk, hk, M, g, tau, steps, inflow):
     print(f"ho2d nx={nx} nk={nk} steps={steps} inflow={inflow}", flush=True)

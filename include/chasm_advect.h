@@ -81,7 +81,8 @@ typedef enum {
 
 enum {
     CHASM_FLAG_REDUCE_EACH_STEP = 1u << 0,   /* record FP64 diagnostics after every step */
-    CHASM_FLAG_GRAPH = 1u << 1,              /* replay each step as a captured HIP graph */
+    CHASM_FLAG_GRAPH = 1u << 1,              /* replay steps as captured HIP graphs (one graph
+                                                per step, and one per 8 steps for long calls) */
     /* Allocate a second field of the same shape and dtype (the stage field, one more
      * field of device memory, owned by the handle) and run the sweeps out of place:
      * SLAB and PLAIN read f in their first launch and write the stage field, and write

@@ -6,7 +6,9 @@ tuning steps is compared with the most accurate candidate (the largest ghost wid
 then the largest patch): the PMBC truncation error shrinks like |sqrt3 - 2|^g, so a
 smaller g is faster to compute but drifts from the untruncated spline.  The winner is
 the fastest candidate whose result stays within `tol` (relative to max|f|) of that
-reference.  Results can be cached in a JSON file keyed by the grid and dt.
+reference; candidates within `margin` (relative) of the fastest time count as equally
+fast (timing noise on a few steps is about 1 %), and among them the most accurate one
+wins.  Results can be cached in a JSON file keyed by the grid and dt.
 
 Host logic only: every step runs through the C ABI.  Parity of each compiled (M, g)
 with the FP64 oracle is the test suite's job, not the tuner's.
@@ -38,7 +40,7 @@ def candidates(grid: inputs.Grid, dt: float, patches: Sequence[int], ghosts: Seq
 
 def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 16), ghosts=(4, 6, 8),
          schedules=("cube", "slab", "plain"), steps: int = 5, warmup: int = 2, tol: float = 1e-5,
-         device: str = "cuda:0", log=None) -> dict:
+         margin: float = 0.01, device: str = "cuda:0", log=None) -> dict:
     import torch
     dev = torch.device(device)
     stream = torch.cuda.current_stream(dev)
@@ -81,7 +83,8 @@ def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 
     del work, f0, ref
     torch.cuda.empty_cache()
     ok = [c for c in cands if c["ok"]]
-    best = min(ok, key=lambda c: c["ms_per_step"])
+    fastest = min(c["ms_per_step"] for c in ok)
+    best = min((c for c in ok if c["ms_per_step"] <= fastest * (1.0 + margin)), key=lambda c: c["deviation"])
     return {"grid": {"nx": list(grid.nx), "nk": list(grid.nk)}, "dt": dt, "tol": tol, "steps": steps,
             "candidates": cands, "best": best}
 

@@ -144,6 +144,8 @@ struct chasm_advect_s {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph2 = nullptr;     // two cube steps f -> stage -> f (CHASM_FLAG_OUT_OF_PLACE)
     hipGraphExec_t gexec2 = nullptr;
+    hipGraph_t graphk = nullptr;     // kGraphSteps steps in one graph
+    hipGraphExec_t gexeck = nullptr;
     hipStream_t cap_stream = nullptr;
     bool poisoned = false;
 };
@@ -368,6 +370,11 @@ static hipError_t issue_cube_pair(chasm_advect_t h, hipStream_t s)
 
 static bool cube_pairs(const chasm_advect_s* h) { return h->stage && h->schedule == CHASM_SCHED_CUBE; }
 
+// Steps per graph launch for long step counts (CHASM_FLAG_GRAPH): one launch per step
+// leaves a few microseconds between consecutive graphs; within a graph the kernels
+// follow each other directly.
+constexpr int kGraphSteps = 8;
+
 extern "C" {
 
 const char* chasm_advect_last_error(void) { return g_err.c_str(); }
@@ -476,22 +483,21 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
     if (desc->flags & CHASM_FLAG_GRAPH) {
         if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
             return bail(CHASM_EDEVICE, "capture stream creation failed");
-        if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return bail(CHASM_EDEVICE, "hipStreamBeginCapture failed");
-        hipError_t ce = issue_step(h, h->cap_stream);
-        hipError_t ee = hipStreamEndCapture(h->cap_stream, &h->graph);
-        if (ce != hipSuccess || ee != hipSuccess) return bail(CHASM_EDEVICE, "step capture failed");
-        if (hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0) != hipSuccess)
-            return bail(CHASM_EDEVICE, "hipGraphInstantiate failed");
-        if (cube_pairs(h)) {
-            if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-                return bail(CHASM_EDEVICE, "hipStreamBeginCapture failed");
-            ce = issue_cube_pair(h, h->cap_stream);
-            ee = hipStreamEndCapture(h->cap_stream, &h->graph2);
-            if (ce != hipSuccess || ee != hipSuccess) return bail(CHASM_EDEVICE, "step-pair capture failed");
-            if (hipGraphInstantiate(&h->gexec2, h->graph2, nullptr, nullptr, 0) != hipSuccess)
-                return bail(CHASM_EDEVICE, "hipGraphInstantiate failed");
-        }
+        // Capture `steps` steps (pairs when the CUBE steps run out of place) as one graph.
+        auto capture = [&](int steps, hipGraph_t* g, hipGraphExec_t* x) {
+            if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+            hipError_t ce = hipSuccess;
+            for (int i = 0; i < steps && ce == hipSuccess;) {
+                const bool pair = cube_pairs(h) && i + 1 < steps;
+                ce = pair ? issue_cube_pair(h, h->cap_stream) : issue_step(h, h->cap_stream);
+                i += pair ? 2 : 1;
+            }
+            const hipError_t ee = hipStreamEndCapture(h->cap_stream, g);
+            return ce == hipSuccess && ee == hipSuccess && hipGraphInstantiate(x, *g, nullptr, nullptr, 0) == hipSuccess;
+        };
+        if (!capture(1, &h->graph, &h->gexec)) return bail(CHASM_EDEVICE, "step capture failed");
+        if (cube_pairs(h) && !capture(2, &h->graph2, &h->gexec2)) return bail(CHASM_EDEVICE, "step-pair capture failed");
+        if (!capture(kGraphSteps, &h->graphk, &h->gexeck)) return bail(CHASM_EDEVICE, "multi-step capture failed");
     }
     *out = h;
     return CHASM_OK;
@@ -503,6 +509,11 @@ chasm_status chasm_advect_step(chasm_advect_t h, int32_t nsteps)
     if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
     if (nsteps < 0) return fail(CHASM_EINVAL, "nsteps must be >= 0");
     int32_t s = 0;
+    if (h->gexeck)
+        for (; s + kGraphSteps <= nsteps; s += kGraphSteps) {
+            hipError_t e = hipGraphLaunch(h->gexeck, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "step launch");
+        }
     if (cube_pairs(h))
         for (; s + 1 < nsteps; s += 2) {
             hipError_t e = h->gexec2 ? hipGraphLaunch(h->gexec2, h->stream) : issue_cube_pair(h, h->stream);
@@ -689,6 +700,8 @@ chasm_status chasm_advect_destroy(chasm_advect_t h)
     if (h->graph) hipGraphDestroy(h->graph);
     if (h->gexec2) hipGraphExecDestroy(h->gexec2);
     if (h->graph2) hipGraphDestroy(h->graph2);
+    if (h->gexeck) hipGraphExecDestroy(h->gexeck);
+    if (h->graphk) hipGraphDestroy(h->graphk);
     if (h->stage) hipFree(h->stage);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->tables) hipFree(h->tables);

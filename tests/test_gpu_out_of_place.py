@@ -33,7 +33,7 @@ CASES = [  # (N, M, g, nk, schedules)
 
 
 @pytest.mark.parametrize("N,M,g,nk,scheds", CASES)
-@pytest.mark.parametrize("steps", [1, 2, 3, 5])
+@pytest.mark.parametrize("steps", [1, 2, 3, 5, 19])
 def test_out_of_place_equals_in_place(N, M, g, nk, scheds, steps):
     grid = inputs.cubic_grid(N, N * 0.4, nk, 3.0)
     dt = 0.45

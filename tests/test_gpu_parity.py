@@ -232,11 +232,12 @@ def test_graph_replay_equals_eager_bitwise():
     f0 = inputs.gaussian_field(w.grid, w.packets, dtype=torch.float32)
     a_out, b_out = f0.to(DEV), f0.to(DEV)
     with chasm.Advect(a_out, w.grid, w.patch, w.ghost, w.dt) as a:
-        a.step(7)
+        a.step(27)
     with chasm.Advect(b_out, w.grid, w.patch, w.ghost, w.dt, graph=True) as b:
         b.step(3)
         torch.cuda.synchronize()
         b.step(4)
+        b.step(20)                  # two 8-step graphs and four single-step graphs
     torch.cuda.synchronize()
     assert torch.equal(a_out, b_out)
 

@@ -1,6 +1,8 @@
-"""Autotuner: pick patch size, ghost width and kernel schedule for a grid.
+"""Autotuner: pick patch size, ghost width, kernel schedule and field placement for a
+grid.
 
-Every candidate (patch M, ghost g, schedule) that has compiled kernels is timed on the
+Every candidate (patch M, ghost g, schedule, in place or out of place through a second
+field) that has compiled kernels is timed on the
 workload's own field (HIP events around graph-replayed steps) and its result after the
 tuning steps is compared with the most accurate candidate (the largest ghost width,
 then the largest patch): the PMBC truncation error shrinks like |sqrt3 - 2|^g, so a
@@ -8,7 +10,8 @@ smaller g is faster to compute but drifts from the untruncated spline.  The winn
 the fastest candidate whose result stays within `tol` (relative to max|f|) of that
 reference; candidates within `margin` (relative) of the fastest time count as equally
 fast (timing noise on a few steps is about 1 %), and among them the most accurate one
-wins.  Results can be cached in a JSON file keyed by the grid and dt.
+wins (in place is listed before out of place, so the second field is taken only when
+it is faster by more than the margin).  Results can be cached in a JSON file keyed by the grid and dt.
 
 Host logic only: every step runs through the C ABI.  Parity of each compiled (M, g)
 with the FP64 oracle is the test suite's job, not the tuner's.
@@ -24,7 +27,7 @@ from . import chasm, inputs
 
 
 def candidates(grid: inputs.Grid, dt: float, patches: Sequence[int], ghosts: Sequence[int],
-               schedules: Sequence[str]) -> List[dict]:
+               schedules: Sequence[str], placements: Sequence[bool] = (False, True)) -> List[dict]:
     out = []
     for M in patches:
         for g in ghosts:
@@ -34,17 +37,18 @@ def candidates(grid: inputs.Grid, dt: float, patches: Sequence[int], ghosts: Seq
                     chasm.chasm_advect_workspace_bytes(d)
                 except chasm.ChasmError:
                     continue
-                out.append({"patch": M, "ghost": g, "schedule": sc})
+                for oop in placements:
+                    out.append({"patch": M, "ghost": g, "schedule": sc, "out_of_place": oop})
     return out
 
 
 def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 16), ghosts=(4, 6, 8),
-         schedules=("cube", "slab", "plain"), steps: int = 5, warmup: int = 2, tol: float = 1e-5,
-         margin: float = 0.01, device: str = "cuda:0", log=None) -> dict:
+         schedules=("cube", "slab", "plain"), placements=(False, True), steps: int = 5, warmup: int = 2,
+         tol: float = 1e-5, margin: float = 0.01, device: str = "cuda:0", log=None) -> dict:
     import torch
     dev = torch.device(device)
     stream = torch.cuda.current_stream(dev)
-    cands = candidates(grid, dt, patches, ghosts, schedules)
+    cands = candidates(grid, dt, patches, ghosts, schedules, placements)
     if not cands:
         raise ValueError("no compiled kernels for this grid")
     f0 = torch.empty(grid.shape(), dtype=torch.float32, device=dev)
@@ -52,13 +56,13 @@ def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 
     inputs.fill_separable(f0, coef, gx, gk)
     work = torch.empty_like(f0)
     # most accurate first: largest ghost width, then largest patch
-    cands.sort(key=lambda c: (-c["ghost"], -c["patch"], c["schedule"]))
+    cands.sort(key=lambda c: (-c["ghost"], -c["patch"], c["schedule"], c["out_of_place"]))
     ref = None
     scale = None
     for c in cands:
         work.copy_(f0)
         adv = chasm.Advect(work, grid, c["patch"], c["ghost"], dt, schedule=c["schedule"], graph=True,
-                           stream=stream)
+                           stream=stream, out_of_place=c["out_of_place"])
         adv.step(warmup)
         torch.cuda.synchronize()
         work.copy_(f0)
@@ -78,7 +82,8 @@ def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 
             c["deviation"] = float((work - ref).abs().max()) / scale
         c["ok"] = c["deviation"] <= tol
         if log:
-            log(f"  M={c['patch']:2d} g={c['ghost']} {c['schedule']:5s} {c['ms_per_step']:8.3f} ms/step "
+            log(f"  M={c['patch']:2d} g={c['ghost']} {c['schedule']:5s} {'oop' if c['out_of_place'] else 'inp'} "
+                f"{c['ms_per_step']:8.3f} ms/step "
                 f"dev={c['deviation']:.2e}{'' if c['ok'] else '  (over tol)'}")
     del work, f0, ref
     torch.cuda.empty_cache()

@@ -146,6 +146,9 @@ struct chasm_advect_s {
     hipGraphExec_t gexec2 = nullptr;
     hipGraph_t graphk = nullptr;     // kGraphSteps steps in one graph
     hipGraphExec_t gexeck = nullptr;
+    hipGraph_t graph_r = nullptr;    // one CUBE step visiting the items last to first
+    hipGraphExec_t gexec_r = nullptr;
+    bool rev_next = false;           // the next CUBE step of chasm_advect_step visits in reverse
     hipStream_t cap_stream = nullptr;
     bool poisoned = false;
 };
@@ -343,24 +346,36 @@ static hipError_t launch_finalize(chasm_advect_s* h, long long rows, bool record
     return hipGetLastError();
 }
 
-static hipError_t issue_step(chasm_advect_t h, hipStream_t s)
+// rev: a CUBE step visits the items last to first.  chasm_advect_step alternates the
+// order from step to step, so the items a step stores last are the first ones the next
+// step loads, while they may still sit in the memory-side cache.
+static hipError_t issue_step(chasm_advect_t h, hipStream_t s, bool rev = false)
 {
     const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
     double* part = red ? h->partials : nullptr;
     const Work* pw[3];
     step_passes(h, pw);
+    Work wr;
+    if (rev && h->schedule == CHASM_SCHED_CUBE) {
+        wr = *pw[0];
+        for (int j = 0; j < wr.njobs; ++j) wr.jobs[j].reverse = 1;
+        pw[0] = pw[1] = pw[2] = &wr;
+    }
     hipError_t e = launch_step(h->ks, h->schedule, pw, part, s);
     if (e == hipSuccess && red) e = launch_finalize(h, h->partial_rows, true, s);
     return e;
 }
 
-// Two CUBE steps out of place: f -> stage, then stage -> f.
+// Two CUBE steps out of place: f -> stage (first item first), then stage -> f (last
+// item first).
 static hipError_t issue_cube_pair(chasm_advect_t h, hipStream_t s)
 {
     const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
     double* part = red ? h->partials : nullptr;
+    Work back = h->w_sf;
+    back.jobs[0].reverse = 1;
     const Work* first[3] = {&h->w_fs, &h->w_fs, &h->w_fs};
-    const Work* second[3] = {&h->w_sf, &h->w_sf, &h->w_sf};
+    const Work* second[3] = {&back, &back, &back};
     hipError_t e = launch_step(h->ks, CHASM_SCHED_CUBE, first, part, s);
     if (e == hipSuccess && red) e = launch_finalize(h, h->partial_rows, true, s);
     if (e == hipSuccess) e = launch_step(h->ks, CHASM_SCHED_CUBE, second, part, s);
@@ -489,13 +504,22 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
             hipError_t ce = hipSuccess;
             for (int i = 0; i < steps && ce == hipSuccess;) {
                 const bool pair = cube_pairs(h) && i + 1 < steps;
-                ce = pair ? issue_cube_pair(h, h->cap_stream) : issue_step(h, h->cap_stream);
+                ce = pair ? issue_cube_pair(h, h->cap_stream) : issue_step(h, h->cap_stream, (i % 2) == 1);
                 i += pair ? 2 : 1;
             }
             const hipError_t ee = hipStreamEndCapture(h->cap_stream, g);
             return ce == hipSuccess && ee == hipSuccess && hipGraphInstantiate(x, *g, nullptr, nullptr, 0) == hipSuccess;
         };
         if (!capture(1, &h->graph, &h->gexec)) return bail(CHASM_EDEVICE, "step capture failed");
+        if (h->schedule == CHASM_SCHED_CUBE) {   // the reversed single step
+            if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return bail(CHASM_EDEVICE, "hipStreamBeginCapture failed");
+            const hipError_t ce = issue_step(h, h->cap_stream, true);
+            const hipError_t ee = hipStreamEndCapture(h->cap_stream, &h->graph_r);
+            if (ce != hipSuccess || ee != hipSuccess ||
+                hipGraphInstantiate(&h->gexec_r, h->graph_r, nullptr, nullptr, 0) != hipSuccess)
+                return bail(CHASM_EDEVICE, "step capture failed");
+        }
         if (cube_pairs(h) && !capture(2, &h->graph2, &h->gexec2)) return bail(CHASM_EDEVICE, "step-pair capture failed");
         if (!capture(kGraphSteps, &h->graphk, &h->gexeck)) return bail(CHASM_EDEVICE, "multi-step capture failed");
     }
@@ -508,7 +532,21 @@ chasm_status chasm_advect_step(chasm_advect_t h, int32_t nsteps)
     if (!h) return fail(CHASM_EINVAL, "handle is NULL");
     if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
     if (nsteps < 0) return fail(CHASM_EINVAL, "nsteps must be >= 0");
+    const bool cube = h->schedule == CHASM_SCHED_CUBE;
+    // One step in the current visiting order; the order alternates for CUBE.
+    auto single = [&]() {
+        const bool rev = cube && h->rev_next;
+        hipError_t e = h->gexec ? hipGraphLaunch(rev ? h->gexec_r : h->gexec, h->stream) : issue_step(h, h->stream, rev);
+        h->rev_next = cube && !h->rev_next;
+        return e;
+    };
     int32_t s = 0;
+    if (h->rev_next && nsteps > 0) {   // realign: the multi-step graphs and pairs start forward
+        hipError_t e = single();
+        if (e != hipSuccess) return hip_fail(h, e, "step launch");
+        s = 1;
+    }
+    // Even-length groups below keep the order's parity.
     if (h->gexeck)
         for (; s + kGraphSteps <= nsteps; s += kGraphSteps) {
             hipError_t e = hipGraphLaunch(h->gexeck, h->stream);
@@ -520,7 +558,7 @@ chasm_status chasm_advect_step(chasm_advect_t h, int32_t nsteps)
             if (e != hipSuccess) return hip_fail(h, e, "step launch");
         }
     for (; s < nsteps; ++s) {
-        hipError_t e = h->gexec ? hipGraphLaunch(h->gexec, h->stream) : issue_step(h, h->stream);
+        hipError_t e = single();
         if (e != hipSuccess) return hip_fail(h, e, "step launch");
     }
     return CHASM_OK;
@@ -702,6 +740,8 @@ chasm_status chasm_advect_destroy(chasm_advect_t h)
     if (h->graph2) hipGraphDestroy(h->graph2);
     if (h->gexeck) hipGraphExecDestroy(h->gexeck);
     if (h->graphk) hipGraphDestroy(h->graphk);
+    if (h->gexec_r) hipGraphExecDestroy(h->gexec_r);
+    if (h->graph_r) hipGraphDestroy(h->graph_r);
     if (h->stage) hipFree(h->stage);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->tables) hipFree(h->tables);

@@ -36,6 +36,7 @@ struct AxisTabDev {
 struct JobDev {
     void* f;               // field base the pass reads
     void* out;             // base the pass writes: f (in place) or a field of the same shape
+    int reverse;           // k_cube visits this job's items last to first
     long long nitems;      // nbatch * nk1 * nk2 * nk3
     int nk[3];
     AxisTabDev ax[3];
@@ -97,15 +98,20 @@ __device__ __forceinline__ void vset<double>(double2& v, int i, double x)
 // offset (VGPR) and a uniform byte offset (SGPR), so a strided line needs no
 // per-element 64-bit address registers.  Out-of-range accesses load 0 and drop
 // stores (hardware range check against the resource size).
-// Cache policy of the field's buffer loads and stores (k_cube, k_pencil): every field
-// value is read once and written once per launch, so they are streamed (the
-// nontemporal bit of the buffer intrinsics' aux operand; 0 would be default caching).
-// Measured: the x3 pencil pass on C3 is 8 % faster streamed, C2 is unchanged, results
-// are bitwise equal.  The slab kernel keeps default caching (streaming its strided
-// scalar stores raised its write traffic by 4 %).
-#ifndef CHASM_FIELD_CPOL
-#define CHASM_FIELD_CPOL 2
-#endif
+// Cache policy of the field's buffer loads and stores (the aux operand of the buffer
+// intrinsics: 2 sets the nontemporal bit, 0 is default caching).
+//  - k_pencil streams (kCpolStream): every field value is read once and written once
+//    per launch; measured 8 % faster on the C3 x3 pass than default caching.
+//  - k_cube caches (kCpolCube): consecutive steps visit the items in opposite orders,
+//    so the cubes a step stores last are loaded first by the next step and can still
+//    be in the memory-side cache; streamed accesses do not allocate there.  Measured
+//    on C2 (537 MB field): 0.194 ms per step streamed in either order, 0.181 ms with
+//    default caching and alternating order.
+//  - k_slab keeps plain vector accesses (streaming its strided scalar stores raised its
+//    write traffic by 4 %).
+// Results are bitwise equal under every policy.
+constexpr int kCpolStream = 2;
+constexpr int kCpolCube = 0;
 
 struct Buf {
     __amdgpu_buffer_rsrc_t r;
@@ -113,35 +119,35 @@ struct Buf {
         : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000))
     {
     }
-    template <typename T>
+    template <typename T, int CP = kCpolStream>
     __device__ __forceinline__ T load(uint32_t voff, uint32_t soff) const
     {
         if constexpr (sizeof(T) == 4) {
-            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, CHASM_FIELD_CPOL));
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, CP));
         } else {
-            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, CHASM_FIELD_CPOL));
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, CP));
         }
     }
-    template <typename T>
+    template <typename T, int CP>
     __device__ __forceinline__ typename Vec16<T>::type load16(uint32_t voff, uint32_t soff) const
     {
         return __builtin_bit_cast(typename Vec16<T>::type,
-                                  __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, CHASM_FIELD_CPOL));
+                                  __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, CP));
     }
-    template <typename T>
+    template <typename T, int CP>
     __device__ __forceinline__ void store16(const typename Vec16<T>::type& x, uint32_t voff, uint32_t soff) const
     {
         using I4 = int __attribute__((ext_vector_type(4)));
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(I4, x), r, (int)voff, (int)soff, CHASM_FIELD_CPOL);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(I4, x), r, (int)voff, (int)soff, CP);
     }
-    template <typename T>
+    template <typename T, int CP = kCpolStream>
     __device__ __forceinline__ void store(T x, uint32_t voff, uint32_t soff) const
     {
         if constexpr (sizeof(T) == 4) {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, x), r, (int)voff, (int)soff, CHASM_FIELD_CPOL);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, x), r, (int)voff, (int)soff, CP);
         } else {
             using I2 = int __attribute__((ext_vector_type(2)));
-            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(I2, x), r, (int)voff, (int)soff, CHASM_FIELD_CPOL);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(I2, x), r, (int)voff, (int)soff, CP);
         }
     }
 };
@@ -254,16 +260,23 @@ __global__ __launch_bounds__(NT) void k_cube(const Work w, double* __restrict__ 
     unsigned tid = threadIdx.x;
     V pre[RV];
     const long long total = w.first[w.njobs];
+    // Item `it` of the visiting order: its job and index in the job (reversed jobs are
+    // visited last item first).
+    auto locate = [&](long long it, long long& local) -> const JobDev& {
+        const JobDev& jb = job_of(w, it, local);
+        if (jb.reverse) local = jb.nitems - 1 - local;
+        return jb;
+    };
     auto cube_of = [&](long long it) {
         long long local;
-        const JobDev& jb = job_of(w, it, local);
+        const JobDev& jb = locate(it, local);
         return static_cast<T*>(jb.f) + local * (long long)(N * N * N);
     };
     auto fetch = [&](long long it, int round) {
         const Buf b(cube_of(it), CUBE_BYTES);
         static_for<0, RV>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            pre[q] = b.template load16<T>(tid * 16u, (uint32_t)((round * RV + q) * NT * 16));
+            pre[q] = b.template load16<T, kCpolCube>(tid * 16u, (uint32_t)((round * RV + q) * NT * 16));
         });
     };
 
@@ -293,7 +306,7 @@ __global__ __launch_bounds__(NT) void k_cube(const Work w, double* __restrict__ 
         const unsigned plane_t = tid / N, lane_t = tid % N;
         const long long next = item + gridDim.x;
         long long local;
-        const JobDev& job = job_of(w, item, local);
+        const JobDev& job = locate(item, local);
         int ik[3];
         item_k(job, local, ik);
         int sig0, sig1;
@@ -376,14 +389,16 @@ __global__ __launch_bounds__(NT) void k_cube(const Work w, double* __restrict__ 
         });
         if constexpr (RED) {
             acc[2] = fma((double)x1_t, acc[0], acc[2]);   // sum (x1_t + i) f
-            write_partials<NT>(acc, ik, partials + item * NRED);
+            long long local0;
+            job_of(w, item, local0);
+            write_partials<NT>(acc, ik, partials + (item - local0 + local) * NRED);   // row of the stored item
         }
         __syncthreads();
         if (next < total) fill(0);
         const Buf b(static_cast<T*>(job.out) + local * (long long)(N * N * N), CUBE_BYTES);
         static_for<0, NV / NT>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            b.template store16<T>(out[q], tid * 16u, (uint32_t)(q * NT * 16));
+            b.template store16<T, kCpolCube>(out[q], tid * 16u, (uint32_t)(q * NT * 16));
         });
         if (next >= total) break;
         item = next;

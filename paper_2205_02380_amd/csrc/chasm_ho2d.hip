@@ -190,7 +190,7 @@ struct DkShape {
     static constexpr int RS = L2 + 1;                // LDS row of [k1][n2], padded
 };
 
-// MODE 0: out = omega x d_k a.  MODE 1: y = a + tau b, out = a + tau/2 (b + omega x d_k y).
+// MODE 0: out = omega x d_k a.  MODE 1: y = a + tau b, out = (a + tau/2 b) + tau/2 omega x d_k y.
 // tw[j] = e^{+2 pi i j / L}.  Index convention of the four-step transform: element
 // n = L2 n1 + n2, frequency m = k1 + L1 k2.  Each lane reads and writes its own
 // elements in HBM (one wave per block, so the block count, not the run length of a
@@ -210,8 +210,11 @@ __global__ __launch_bounds__(64) void k_ho_dk(const double* __restrict__ a, cons
     const int xa = 2 * (blockIdx.x * S::CLB + cl), xb = xa + 1;
     const bool has_a = xa < p.nx, has_b = xb < p.nx;
     cd* Y = lds + cl * L1 * S::RS;
-    auto input = [&](long long i) { return MODE == 0 ? a[i] : fma(p.tau, b[i], a[i]); };
 
+    // MODE 1 keeps a + tau/2 b of the thread's output elements from step 1 to step 3
+    // (the same rows and columns), so step 3 issues no dependent loads.
+    const double h = 0.5 * p.tau;
+    cd keep[MODE == 1 ? L1 : 1];
     // Step 1 (thread n2 = lt): L1-point transforms over n1, twiddle e^{-2 pi i n2 k1 / L}.
     if (lt < L2 && has_a) {
         const int n2 = lt;
@@ -219,7 +222,14 @@ __global__ __launch_bounds__(64) void k_ho_dk(const double* __restrict__ a, cons
         sfor<0, L1>([&](auto ic) {
             constexpr int n1 = decltype(ic)::value;
             const long long row = (long long)(L2 * n1 + n2) * p.nx;
-            v[n1] = {input(row + xa), has_b ? input(row + xb) : 0.0};
+            if constexpr (MODE == 0) {
+                v[n1] = {a[row + xa], has_b ? a[row + xb] : 0.0};
+            } else {
+                const double aa = a[row + xa], ba = b[row + xa];
+                const double ab = has_b ? a[row + xb] : 0.0, bb = has_b ? b[row + xb] : 0.0;
+                v[n1] = {fma(p.tau, ba, aa), fma(p.tau, bb, ab)};
+                keep[n1] = {fma(h, ba, aa), fma(h, bb, ab)};
+            }
         });
         transform<L1, -1>(v);
         sfor<0, L1>([&](auto kc) {
@@ -268,9 +278,8 @@ __global__ __launch_bounds__(64) void k_ho_dk(const double* __restrict__ a, cons
                 out[row + xa] = fa * v[n1].re;
                 if (has_b) out[row + xb] = fb * v[n1].im;
             } else {
-                const double h = 0.5 * p.tau;
-                out[row + xa] = fma(h, b[row + xa] + fa * v[n1].re, a[row + xa]);
-                if (has_b) out[row + xb] = fma(h, b[row + xb] + fb * v[n1].im, a[row + xb]);
+                out[row + xa] = fma(h, fa * v[n1].re, keep[n1].re);
+                if (has_b) out[row + xb] = fma(h, fb * v[n1].im, keep[n1].im);
             }
         });
     }

@@ -37,7 +37,7 @@ extern "C" {
 typedef struct chasm_ho2d_s* chasm_ho2d_t;   /* opaque handle */
 
 typedef struct {
-    int32_t nx;            /* x nodes, 2 .. 1024, and 8 (2 nx + 4 P) doubles <= 64 KiB (nx <= ~500) */
+    int32_t nx;            /* x nodes, 2 .. 1024 */
     double x_lo, hx;
     int32_t nk;            /* k nodes, even, 2 .. 4096 */
     double k_lo, hk;

@@ -47,7 +47,7 @@ struct HoArgs {
     const double* w;           // nk x 4
 };
 
-constexpr int HO_LB = 8;       // lines per block
+constexpr int HO_LB = 2;       // lines per block (measured at nx = 241, 1024 lines: 8 -> 21.5 us, 4 -> 15.7, 2 -> 14.7)
 
 __global__ __launch_bounds__(256) void k_ho_advect(const double* __restrict__ in, double* __restrict__ out, const HoArgs a,
                                                   int nlines)
@@ -413,7 +413,7 @@ chasm_status chasm_ho2d_create(const chasm_ho2d_desc* d, void* f_dev, void* hip_
         return hfail(CHASM_EINVAL, err);
     const int P = at.P, M = d->patch, mlast = at.MLAST;
     if ((size_t)HO_LB * (2 * d->nx + 4 * P) * sizeof(double) > 65536)
-        return hfail(CHASM_EINVAL, "lines too long for the LDS line kernel (8 lines of 2 nx + 4 P doubles <= 64 KiB)");
+        return hfail(CHASM_EINVAL, "lines too long for the LDS line kernel (2 lines of 2 nx + 4 P doubles <= 64 KiB)");
     const bool by_transform = dk_by_transform(d->nk);
     const std::vector<double> AM = patch_inverse(M), AL = patch_inverse(mlast);
     const std::vector<double> D = by_transform ? std::vector<double>() : spectral_dk(d->nk, d->hk);

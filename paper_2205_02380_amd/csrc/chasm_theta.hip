@@ -127,10 +127,15 @@ static void tensor_positive(const int nk[3], const double hk[3], std::vector<dou
             }
 }
 
-// Transform of T placed circularly with period P_d = 2 nk_d (entries at |q_d| = nk_d
-// are zero): That(xi) = sum_q T_q cos(2 pi q.xi / P), real since T is even.  Output
-// [xi1][xi2][xi3] (xi3 fastest), the order the kernel reads it in.
-static void tensor_transform(const int nk[3], const std::vector<double>& T, std::vector<double>& That)
+// T placed circularly with period P_d = 2 nk_d (entries at |q_d| = nk_d are zero),
+// transformed along k1 and k2 only: B(xi1, xi2, q3) = sum_{q1, q2} T_q cos(2 pi (q1 xi1 /
+// P1 + q2 xi2 / P2)), real since T is even in each coordinate.  The full transform would
+// be That(xi) = sum_{|q3| < nk3} B(xi1, xi2, |q3|) e^{2 pi i q3 xi3 / P3}, so transforming
+// a zero-padded k3 line, multiplying by That and transforming back (without 1/P3) gives,
+// at the first nk3 outputs, o_j = sum_j' P3 B(xi1, xi2, |j - j'|) row_j'.  Output
+// kt[xi1][xi2][q3] = P3 B(xi1, xi2, q3), q3 < nk3 (q3 fastest), the order the kernel
+// reads it in.
+static void tensor_partial(const int nk[3], const std::vector<double>& T, std::vector<double>& kt)
 {
     const int P[3] = {2 * nk[0], 2 * nk[1], 2 * nk[2]};
     // per axis: g(xi) = g(0) + 2 sum_{q=1}^{nk-1} g(q) cos(2 pi q xi / P)
@@ -143,21 +148,13 @@ static void tensor_transform(const int nk[3], const std::vector<double>& T, std:
                 for (int q1 = 0; q1 < nk[0]; ++q1) s += T[((size_t)q3 * nk[1] + q2) * nk[0] + q1] * wcos(0, q1, f1);
                 B1[((size_t)q3 * nk[1] + q2) * P[0] + f1] = s;
             }
-    std::vector<double> B2((size_t)nk[2] * P[1] * P[0]);    // [q3][xi2][xi1]
+    kt.assign((size_t)P[0] * P[1] * nk[2], 0.0);
     for (int q3 = 0; q3 < nk[2]; ++q3)
         for (int f2 = 0; f2 < P[1]; ++f2)
             for (int f1 = 0; f1 < P[0]; ++f1) {
                 double s = 0.0;
                 for (int q2 = 0; q2 < nk[1]; ++q2) s += B1[((size_t)q3 * nk[1] + q2) * P[0] + f1] * wcos(1, q2, f2);
-                B2[((size_t)q3 * P[1] + f2) * P[0] + f1] = s;
-            }
-    That.assign((size_t)P[0] * P[1] * P[2], 0.0);
-    for (int f1 = 0; f1 < P[0]; ++f1)
-        for (int f2 = 0; f2 < P[1]; ++f2)
-            for (int f3 = 0; f3 < P[2]; ++f3) {
-                double s = 0.0;
-                for (int q3 = 0; q3 < nk[2]; ++q3) s += B2[((size_t)q3 * P[1] + f2) * P[0] + f1] * wcos(2, q3, f3);
-                That[((size_t)f1 * P[1] + f2) * P[2] + f3] = s;
+                kt[((size_t)f1 * P[1] + f2) * nk[2] + q3] = P[2] * s;
             }
 }
 
@@ -165,7 +162,7 @@ static void tensor_transform(const int nk[3], const std::vector<double>& T, std:
 // Compiled kernels: (storage type, nk) -> chunk count R and block size.
 struct ThetaKernels {
     int dtype, nk;
-    hipError_t (*theta)(void* fx, const double* that, const ThetaArgs& a, long long total, hipStream_t s);
+    hipError_t (*theta)(void* fx, const double* kt, const ThetaArgs& a, long long total, hipStream_t s);
     hipError_t (*transpose)(const void* in, void* out, long long rows, long long cols, int batch, hipStream_t s);
 };
 
@@ -180,12 +177,12 @@ static long long resident(K k, int threads)
 }
 
 template <typename T, int NK, int R, int NT>
-static hipError_t launch_theta(void* fx, const double* that, const ThetaArgs& a, long long total, hipStream_t s)
+static hipError_t launch_theta(void* fx, const double* kt, const ThetaArgs& a, long long total, hipStream_t s)
 {
     auto k = k_theta<T, NK, R, NT>;
     const long long res = resident(k, NT);
     const unsigned grid = (unsigned)(res > 0 && res < total ? res : total);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(NT), 0, s, static_cast<T*>(fx), that, a, total);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(NT), 0, s, static_cast<T*>(fx), kt, a, total);
     return hipGetLastError();
 }
 
@@ -220,7 +217,7 @@ struct chasm_theta_s {
     chasm_theta_desc desc;
     hipStream_t stream = nullptr;
     const ThetaKernels* ks = nullptr;
-    double* that = nullptr;
+    double* kt = nullptr;               // kernel transformed along k1, k2 (tensor_partial)
     void* ws = nullptr;
     ThetaArgs args{};
     long long npts = 0, nkp = 0;
@@ -315,9 +312,9 @@ chasm_status chasm_theta_create(const chasm_theta_desc* desc, void* hip_stream, 
     int nk[3];
     double hk[3];
     desc_hk(desc, nk, hk);
-    std::vector<double> T, That;
+    std::vector<double> T, KT;
     tensor_positive(nk, hk, T);
-    tensor_transform(nk, T, That);
+    tensor_partial(nk, T, KT);
 
     chasm_theta_s* h = new (std::nothrow) chasm_theta_s();
     if (!h) return tfail(CHASM_ENOMEM, "host allocation failed");
@@ -330,9 +327,9 @@ chasm_status chasm_theta_create(const chasm_theta_desc* desc, void* hip_stream, 
         chasm_theta_destroy(h);
         return tfail(s, m);
     };
-    if (hipMalloc((void**)&h->that, That.size() * sizeof(double)) != hipSuccess)
+    if (hipMalloc((void**)&h->kt, KT.size() * sizeof(double)) != hipSuccess)
         return bail(CHASM_ENOMEM, "hipMalloc(symbol) failed");
-    if (hipMemcpyAsync(h->that, That.data(), That.size() * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
+    if (hipMemcpyAsync(h->kt, KT.data(), KT.size() * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
         hipSuccess)
         return bail(CHASM_EDEVICE, "symbol upload failed");
     const size_t es = desc->dtype == CHASM_F64 ? 8 : 4;
@@ -364,7 +361,7 @@ chasm_status chasm_theta_apply(chasm_theta_t h, const void* f_dev, void* out_dev
     if (h->poisoned) return tfail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
     const int nb = h->desc.nbatch;
     hipError_t e = h->ks->transpose(f_dev, h->ws, h->nkp, h->npts, nb, h->stream);
-    if (e == hipSuccess) e = h->ks->theta(h->ws, h->that, h->args, h->npts * nb, h->stream);
+    if (e == hipSuccess) e = h->ks->theta(h->ws, h->kt, h->args, h->npts * nb, h->stream);
     if (e == hipSuccess) e = h->ks->transpose(h->ws, out_dev, h->npts, h->nkp, nb, h->stream);
     if (e != hipSuccess) {
         h->poisoned = true;
@@ -377,7 +374,7 @@ chasm_status chasm_theta_destroy(chasm_theta_t h)
 {
     if (!h) return CHASM_OK;
     if (h->stream) hipStreamSynchronize(h->stream);
-    if (h->that) hipFree(h->that);
+    if (h->kt) hipFree(h->kt);
     if (h->ws) hipFree(h->ws);
     delete h;
     return CHASM_OK;

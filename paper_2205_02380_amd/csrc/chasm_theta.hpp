@@ -9,7 +9,8 @@
 // (2N_k - 1)^3 tensor T is a circular one of period P = 2 N_k per axis: forward
 // transform of the zero-padded modulated data, multiplication by That (the P^3
 // transform of T, real because T is real and even), inverse transform, the first N_k
-// outputs per axis.
+// outputs per axis.  Along k3 the transform, multiply and inverse are replaced by the
+// equivalent Toeplitz product (stage C below).
 //
 // One x-point per block at a time (persistent over x-points), FP64 throughout.  The
 // P x P x N_k intermediate of an x-point does not fit in LDS for N_k = 16 in FP64, so
@@ -19,7 +20,11 @@
 // C-point inverse DFT, twiddled, into the accumulator.  Stages per chunk:
 //   A  k1 forward for every (k2, k3) line          -> W1[m][k3][k2]
 //   B  k2 forward (zero-padded, P outputs)          -> W2[m][xi2][k3]
-//   C  k3 forward, times That(xi1, xi2, .), inverse, first N_k outputs (in place)
+//   C  k3 convolution (in place): the first N_k outputs of the period-P circular
+//      convolution of a zero-padded line are the Toeplitz product with the kernel
+//      transformed along k1 and k2 only, K(xi1, xi2, |q3|), q3 < N_k -- the same result
+//      as transform, multiply by That, inverse, in 2 N_k^2 real multiply-adds per line
+//      instead of four N_k-point transforms
 //   D  k2 inverse, first N_k outputs                -> W1[m][k3][k2] + W1o[m][k3][k2]
 //   E  k1 inverse of the chunk, into the accumulator of each (k2, k3) line
 // Rows of W1 and W2 are padded to N_k + 1 complex values, so the row-per-lane stages
@@ -105,7 +110,7 @@ struct ThetaShape {
 // SPLIT: stages B and D as two half-transform work items per line (else one item per
 // line; measured 3 % slower at N_k = 16).
 template <typename T, int NK, int R, int NT, int WPE = 1, bool SPLIT = true>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_theta(T* __restrict__ fx, const double* __restrict__ that, const ThetaArgs a,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_theta(T* __restrict__ fx, const double* __restrict__ kt, const ThetaArgs a,
                                              long long total)
 {
     using namespace fft;
@@ -225,23 +230,36 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                     }
                 }
                 __syncthreads();
-                // ---- C: k3 forward, symbol, inverse (first NK outputs), in place
+                // ---- C: the k3 convolution of every (xi1, xi2) line, in place: the first NK
+                // outputs of the period-P circular convolution of the zero-padded line are
+                // a Toeplitz product with the kernel transformed along k1 and k2 only,
+                // o_j = sum_j' row_j' K(|j - j'|), K real (see kt below)
                 for (int ln = tid; ln < LC; ln += NT) {
                     const int m = ln / P, f2 = ln % P;
-                    cd row[NK], Y[P], o[NK];
+                    cd row[NK], o[NK];
+                    double kk[NK];
+                    const double2* kr = reinterpret_cast<const double2*>(kt + ((long long)(r + R * m) * P + f2) * NK);
+                    sfor<0, NK / 2>([&](auto qc) {
+                        constexpr int q = decltype(qc)::value;
+                        const double2 t = kr[q];
+                        kk[2 * q] = t.x;
+                        kk[2 * q + 1] = t.y;
+                    });
                     sfor<0, NK>([&](auto jc) {
                         constexpr int j = decltype(jc)::value;
                         row[j] = W2[(m * P + f2) * RS + j];
                     });
-                    fft_fwd_padded<NK>(row, Y);
-                    const double2* tr = reinterpret_cast<const double2*>(that + ((long long)(r + R * m) * P + f2) * P);
-                    sfor<0, P / 2>([&](auto fc) {
-                        constexpr int f = decltype(fc)::value;
-                        const double2 t = tr[f];
-                        Y[2 * f] = cd{Y[2 * f].re * t.x, Y[2 * f].im * t.x};
-                        Y[2 * f + 1] = cd{Y[2 * f + 1].re * t.y, Y[2 * f + 1].im * t.y};
+                    sfor<0, NK>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        double re = 0.0, im = 0.0;
+                        sfor<0, NK>([&](auto ic) {
+                            constexpr int i = decltype(ic)::value;
+                            constexpr int d = j > i ? j - i : i - j;
+                            re = fma(kk[d], row[i].re, re);
+                            im = fma(kk[d], row[i].im, im);
+                        });
+                        o[j] = cd{re, im};
                     });
-                    fft_inv_half<NK>(Y, o);
                     sfor<0, NK>([&](auto jc) {
                         constexpr int j = decltype(jc)::value;
                         W2[(m * P + f2) * RS + j] = o[j];

@@ -13,7 +13,7 @@
 //             (N^2 (N+1) values, rows padded to N+1 so x1-, x2- and x3-lines are
 //             bank-conflict free): 8 B/point-update in FP32.
 //   k_slab    x1 sweep, optionally followed by the x2 sweep, on S x3-slabs (N x N)
-//             held in LDS.
+//             held in LDS; persistent, with the next unit's loads in flight.
 //   k_pencil  x2 or x3 sweep; each lane holds one whole line in VGPRs, lanes of a
 //             wave hold neighbouring x1 columns, so every load and store of the
 //             wave is a contiguous run of x1.
@@ -414,65 +414,84 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
     constexpr int PX = N + 1;
     constexpr int NT = S * N;
     constexpr int VW = Vec16<T>::n;
-    static_assert(N % VW == 0 && N % S == 0, "bad slab shape");
+    constexpr int RV = S * N * N / VW / NT;        // 16-byte vectors per lane per unit
+    static_assert(N % VW == 0 && N % S == 0 && (S * N * N / VW) % NT == 0, "bad slab shape");
     using V = typename Vec16<T>::type;
     __shared__ T lds[S * N * PX];
 
-    constexpr int BPI = N / S;                     // blocks per item
-    long long item;
-    const JobDev& job = job_of(w, blockIdx.x / BPI, item);
-    const int slab0 = (blockIdx.x % BPI) * S;
-    int ik[3];
-    item_k(job, item, ik);
-    const long long off = item * (long long)(N * N * N) + (long long)slab0 * N * N;
-    const T* in_ptr = static_cast<const T*>(job.f) + off;
-    T* out_ptr = static_cast<T*>(job.out) + off;
-
-    const V* src = reinterpret_cast<const V*>(in_ptr);
-#pragma unroll
-    for (int e = threadIdx.x; e < S * N * N / VW; e += NT) {
-        const V x = src[e];
-        const int row = (e * VW) / N, x1 = (e * VW) % N;
-#pragma unroll
-        for (int i = 0; i < VW; ++i) lds[row * PX + x1 + i] = vget<T>(x, i);
-    }
-    __syncthreads();
-
-    {
-        int sigma;
-        const auto kc = axis_coef<T>(job, 0, ik[0], sigma);
-        const int base = threadIdx.x * PX;          // row (x2, slab) = (t % N, t / N)
-        dispatch_sigma(sigma, [&](auto sc) {
-            T v[N];
-#pragma unroll
-            for (int i = 0; i < N; ++i) v[i] = lds[base + i];
-            advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { lds[base + j] = x; });
-        });
-    }
-    __syncthreads();
-
-    if (!X2) {
-        V* dst = reinterpret_cast<V*>(out_ptr);
-#pragma unroll
-        for (int e = threadIdx.x; e < S * N * N / VW; e += NT) {
+    // Persistent over units (S consecutive x3-slabs of one item); the next unit's loads
+    // are in flight in VGPRs while this unit is swept and stored.  Units are disjoint,
+    // so in place a prefetch never reads what another unit writes.
+    constexpr int BPI = N / S;                     // units per item
+    const long long units = w.first[w.njobs] * BPI;
+    long long u = blockIdx.x;
+    if (u >= units) return;
+    V pre[RV];
+    auto fetch = [&](long long uu) {
+        long long it;
+        const JobDev& jb = job_of(w, uu / BPI, it);
+        const V* src = reinterpret_cast<const V*>(static_cast<const T*>(jb.f) + it * (long long)(N * N * N) +
+                                                  (long long)(uu % BPI) * S * N * N);
+        static_for<0, RV>([&](auto qc) { pre[decltype(qc)::value] = src[decltype(qc)::value * NT + threadIdx.x]; });
+    };
+    fetch(u);
+    for (;;) {
+        static_for<0, RV>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const int e = q * NT + threadIdx.x;
             const int row = (e * VW) / N, x1 = (e * VW) % N;
-            V x;
 #pragma unroll
-            for (int i = 0; i < VW; ++i) vset<T>(x, i, lds[row * PX + x1 + i]);
-            dst[e] = x;
-        }
-    } else {
-        int sigma;
-        const auto kc = axis_coef<T>(job, 1, ik[1], sigma);
-        const int slab = threadIdx.x / N, col = threadIdx.x % N;
-        const int base = slab * N * PX + col;
-        T* out = out_ptr + slab * N * N + col;
-        dispatch_sigma(sigma, [&](auto sc) {
-            T v[N];
-#pragma unroll
-            for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
-            advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { out[j * N] = x; });
+            for (int i = 0; i < VW; ++i) lds[row * PX + x1 + i] = vget<T>(pre[q], i);
         });
+        __syncthreads();
+        const long long next = u + gridDim.x;
+        if (next < units) fetch(next);
+
+        long long item;
+        const JobDev& job = job_of(w, u / BPI, item);
+        const int slab0 = (int)(u % BPI) * S;
+        int ik[3];
+        item_k(job, item, ik);
+        T* out_ptr = static_cast<T*>(job.out) + item * (long long)(N * N * N) + (long long)slab0 * N * N;
+        {
+            int sigma;
+            const auto kc = axis_coef<T>(job, 0, ik[0], sigma);
+            const int base = threadIdx.x * PX;          // row (x2, slab) = (t % N, t / N)
+            dispatch_sigma(sigma, [&](auto sc) {
+                T v[N];
+#pragma unroll
+                for (int i = 0; i < N; ++i) v[i] = lds[base + i];
+                advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { lds[base + j] = x; });
+            });
+        }
+        __syncthreads();
+
+        if (!X2) {
+            V* dst = reinterpret_cast<V*>(out_ptr);
+#pragma unroll
+            for (int e = threadIdx.x; e < S * N * N / VW; e += NT) {
+                const int row = (e * VW) / N, x1 = (e * VW) % N;
+                V x;
+#pragma unroll
+                for (int i = 0; i < VW; ++i) vset<T>(x, i, lds[row * PX + x1 + i]);
+                dst[e] = x;
+            }
+        } else {
+            int sigma;
+            const auto kc = axis_coef<T>(job, 1, ik[1], sigma);
+            const int slab = threadIdx.x / N, col = threadIdx.x % N;
+            const int base = slab * N * PX + col;
+            T* out = out_ptr + slab * N * N + col;
+            dispatch_sigma(sigma, [&](auto sc) {
+                T v[N];
+#pragma unroll
+                for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
+                advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { out[j * N] = x; });
+            });
+        }
+        if (next >= units) break;
+        __syncthreads();   // the output phase has read the LDS before the next fill
+        u = next;
     }
 }
 

@@ -24,10 +24,10 @@ struct Launch {
     static constexpr int reduce_nt = 256;
 };
 
-// Resident blocks of kernel k on the current device (CUs x blocks per CU), cached
-// per device and kernel.
-template <typename K>
-int resident_blocks(K k, int threads)
+// Resident blocks of kernel K on the current device (CUs x blocks per CU), cached per
+// device; one cache per kernel instantiation.
+template <auto K>
+int resident_blocks(int threads)
 {
     static int cache[64] = {0};
     int dev = 0;
@@ -35,10 +35,20 @@ int resident_blocks(K k, int threads)
     if (cache[dev] == 0) {
         int ncu = 0, per = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, threads, 0) != hipSuccess) return 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, K, threads, 0) != hipSuccess) return 0;
         cache[dev] = ncu * (per > 0 ? per : 1);
     }
     return cache[dev];
+}
+
+// Persistent launch: one block per resident slot, at most one per unit of work.
+template <auto K, typename... A>
+hipError_t launch_persistent(int threads, long long units, hipStream_t s, A... args)
+{
+    const long long res = resident_blocks<K>(threads);
+    const unsigned grid = (unsigned)(res > 0 && res < units ? res : units);
+    hipLaunchKernelGGL(K, dim3(grid), dim3(threads), 0, s, args...);
+    return hipGetLastError();
 }
 
 template <typename T, int N, int M, int G, int CL>
@@ -46,15 +56,10 @@ hipError_t launch_cube(const Work& w, double* partials, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     if constexpr (Lc::cube_fits) {
-        auto launch = [&](auto k) {
-            const long long res = resident_blocks(k, Lc::cube_nt);
-            const long long items = w.first[w.njobs];
-            const unsigned grid = (unsigned)(res > 0 && res < items ? res : items);
-            hipLaunchKernelGGL(k, dim3(grid), dim3(Lc::cube_nt), 0, s, w, partials);
-            return hipGetLastError();
-        };
-        return partials ? launch(k_cube<T, N, M, G, CL, Lc::cube_nt, true>)
-                        : launch(k_cube<T, N, M, G, CL, Lc::cube_nt, false>);
+        constexpr int NT = Lc::cube_nt;
+        const long long items = w.first[w.njobs];
+        return partials ? launch_persistent<k_cube<T, N, M, G, CL, NT, true>>(NT, items, s, w, partials)
+                        : launch_persistent<k_cube<T, N, M, G, CL, NT, false>>(NT, items, s, w, partials);
     } else {
         return hipErrorInvalidConfiguration;
     }
@@ -65,9 +70,7 @@ hipError_t launch_slab(const Work& w, double*, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     constexpr int S = Lc::slab_s;
-    const unsigned grid = (unsigned)(w.first[w.njobs] * (N / S));
-    hipLaunchKernelGGL((k_slab<T, N, M, G, CL, S, X2>), dim3(grid), dim3(S * N), 0, s, w);
-    return hipGetLastError();
+    return launch_persistent<k_slab<T, N, M, G, CL, S, X2>>(S * N, w.first[w.njobs] * (N / S), s, w);
 }
 
 template <typename T, int N, int M, int G, int CL, int AXIS>

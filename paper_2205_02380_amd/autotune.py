@@ -42,6 +42,23 @@ def candidates(grid: inputs.Grid, dt: float, patches: Sequence[int], ghosts: Seq
     return out
 
 
+def accuracy_order(c: dict):
+    """Most accurate first: largest ghost width, then largest patch; in place before out
+    of place (equal results, less memory)."""
+    return (-c["ghost"], -c["patch"], c["schedule"], c["out_of_place"])
+
+
+def choose(cands: List[dict], margin: float = 0.01) -> dict:
+    """Among the candidates within tolerance (`ok`), those within `margin` of the fastest
+    time count as equally fast; of these the one with the smallest deviation wins, ties
+    going to the earliest in accuracy order."""
+    ok = sorted((c for c in cands if c["ok"]), key=accuracy_order)
+    if not ok:
+        raise ValueError("no candidate within tolerance")
+    fastest = min(c["ms_per_step"] for c in ok)
+    return min((c for c in ok if c["ms_per_step"] <= fastest * (1.0 + margin)), key=lambda c: c["deviation"])
+
+
 def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 16), ghosts=(4, 6, 8),
          schedules=("cube", "slab", "plain"), placements=(False, True), steps: int = 5, warmup: int = 2,
          tol: float = 1e-5, margin: float = 0.01, device: str = "cuda:0", log=None) -> dict:
@@ -56,7 +73,7 @@ def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 
     inputs.fill_separable(f0, coef, gx, gk)
     work = torch.empty_like(f0)
     # most accurate first: largest ghost width, then largest patch
-    cands.sort(key=lambda c: (-c["ghost"], -c["patch"], c["schedule"], c["out_of_place"]))
+    cands.sort(key=accuracy_order)
     ref = None
     scale = None
     for c in cands:
@@ -87,9 +104,7 @@ def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 
                 f"dev={c['deviation']:.2e}{'' if c['ok'] else '  (over tol)'}")
     del work, f0, ref
     torch.cuda.empty_cache()
-    ok = [c for c in cands if c["ok"]]
-    fastest = min(c["ms_per_step"] for c in ok)
-    best = min((c for c in ok if c["ms_per_step"] <= fastest * (1.0 + margin)), key=lambda c: c["deviation"])
+    best = choose(cands, margin)
     return {"grid": {"nx": list(grid.nx), "nk": list(grid.nk)}, "dt": dt, "tol": tol, "steps": steps,
             "candidates": cands, "best": best}
 

@@ -189,3 +189,33 @@ def test_compiled_shapes_cover_every_tuned_configuration():
     assert need <= s, need - s
     for dt, n, m, g, cl in s:
         assert n % m == 0 and 1 <= g < n
+
+
+def test_autotune_candidates_weigh_placement():
+    """Every (patch, ghost, schedule) the C3 grid supports appears in place and out of
+    place (48^3 cubes exceed LDS, so no cube schedule)."""
+    from paper_2205_02380_amd import autotune
+    w = inputs.workload("C3")
+    cands = autotune.candidates(w.grid, w.dt, (8, 12, 16), (4, 6, 8), ("cube", "slab", "plain"))
+    keys = {(c["patch"], c["ghost"], c["schedule"]) for c in cands}
+    assert {c["schedule"] for c in cands} == {"slab", "plain"}
+    assert len(cands) == 2 * len(keys) == 36
+
+
+def test_autotune_choice_breaks_timing_ties_by_accuracy():
+    from paper_2205_02380_amd import autotune
+
+    def c(M, g, sc, oop, ms, dev, ok=True):
+        return {"patch": M, "ghost": g, "schedule": sc, "out_of_place": oop, "ms_per_step": ms, "deviation": dev,
+                "ok": ok}
+    cands = [c(16, 8, "slab", False, 4.60, 0.0), c(16, 8, "slab", True, 4.58, 0.0),
+             c(12, 8, "slab", False, 4.57, 2.5e-6), c(16, 4, "slab", False, 4.10, 4e-4, ok=False)]
+    best = autotune.choose(cands, margin=0.01)
+    # within 1 % of the fastest ok time (4.57): the most accurate, in place before out of place
+    assert (best["patch"], best["ghost"], best["out_of_place"]) == (16, 8, False)
+    best = autotune.choose(cands, margin=0.0)
+    assert (best["patch"], best["ghost"]) == (12, 8)
+    cands[1]["ms_per_step"] = 4.40            # out of place clearly faster: it wins
+    assert autotune.choose(cands, margin=0.01)["out_of_place"] is True
+    with pytest.raises(ValueError):
+        autotune.choose([c(8, 4, "slab", False, 1.0, 1.0, ok=False)])

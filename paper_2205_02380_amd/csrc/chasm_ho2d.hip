@@ -18,6 +18,8 @@
 //                i xi / nk (Nyquist mode 0) and the inverse in reverse order, with two
 //                LDS transposes per line.  Mode 1 fuses the LPC1 corrector: it reads
 //                FA, GA, transforms Y = FA + tau GA and writes FA + tau/2 (GA + Theta Y).
+//   k_ho_dk512   nk = 512: the same transform pair in three levels of 8-point
+//                transforms, one complex line per 64-thread block.
 //   k_ho_theta   any other even nk: out[k][x] = omega x sum_q D[k][q] f[q][x], a dense
 //                FP64 contraction with the circulant spectral differentiation matrix,
 //                32 x 32 output tiles staged through LDS, 2 x 2 outputs per thread.
@@ -285,6 +287,104 @@ __global__ __launch_bounds__(64) void k_ho_dk(const double* __restrict__ a, cons
     }
 }
 
+// nk = 512 = 8 x 8 x 8: a three-level form of the same transform pair, so that every
+// thread's serial chain is six 8-point transforms (the four-step form above runs two
+// 32-point transforms per thread in its middle step).  One complex line (x columns 2c,
+// 2c+1) per 64-thread block.  Index convention: element n = 64 n1 + 8 n2 + n3,
+// frequency m = m1 + 8 m2 + 64 m3;
+//   step 1   (n2, n3): 8-point transform over n1, twiddle e^{-2 pi i (8 n2 + n3) m1 / 512}
+//   step 2   (m1, n3): 8-point transform over n2, twiddle e^{-2 pi i 8 n3 m2 / 512}
+//   step 3   (m1, m2): 8-point transform over n3, times i xi_m / 512, inverse over m3
+//   steps 2', 1': the inverses of steps 2 and 1 with conjugate twiddles.
+template <int MODE>
+__global__ __launch_bounds__(64) void k_ho_dk512(const double* __restrict__ a, const double* __restrict__ b,
+                                                double* __restrict__ out, const fft::cd* __restrict__ tw,
+                                                const DkArgs p)
+{
+    using namespace fft;
+    constexpr int L = 512, RS = 65;                 // LDS rows of 64 values, padded
+    __shared__ cd S1[8 * RS];                        // [m1][n3][n2]
+    __shared__ cd S2[8 * RS];                        // [m1][m2][n3]
+    const int t = threadIdx.x, lo = t & 7, hi = t >> 3;
+    const int xa = 2 * blockIdx.x, xb = xa + 1;
+    const bool has_b = xb < p.nx;
+    const double h = 0.5 * p.tau;
+    cd v[8];
+    cd keep[MODE == 1 ? 8 : 1];
+    // step 1: (n2, n3) = (lo, hi)
+    sfor<0, 8>([&](auto ic) {
+        constexpr int n1 = decltype(ic)::value;
+        const long long row = (long long)(64 * n1 + 8 * lo + hi) * p.nx;
+        if constexpr (MODE == 0) {
+            v[n1] = {a[row + xa], has_b ? a[row + xb] : 0.0};
+        } else {
+            const double aa = a[row + xa], ba = b[row + xa];
+            const double ab = has_b ? a[row + xb] : 0.0, bb = has_b ? b[row + xb] : 0.0;
+            v[n1] = {fma(p.tau, ba, aa), fma(p.tau, bb, ab)};
+            keep[n1] = {fma(h, ba, aa), fma(h, bb, ab)};
+        }
+    });
+    transform<8, -1>(v);
+    sfor<0, 8>([&](auto mc) {
+        constexpr int m1 = decltype(mc)::value;
+        cd w = v[m1];
+        if constexpr (m1 > 0) w = cmul(w, conj(tw[((8 * lo + hi) * m1) & (L - 1)]));
+        S1[m1 * RS + 8 * hi + lo] = w;
+    });
+    __syncthreads();
+    // step 2: (m1, n3) = (lo, hi)
+    sfor<0, 8>([&](auto ic) { v[decltype(ic)::value] = S1[lo * RS + 8 * hi + decltype(ic)::value]; });
+    transform<8, -1>(v);
+    sfor<0, 8>([&](auto mc) {
+        constexpr int m2 = decltype(mc)::value;
+        cd w = v[m2];
+        if constexpr (m2 > 0) w = cmul(w, conj(tw[(8 * hi * m2) & (L - 1)]));
+        S2[lo * RS + 8 * m2 + hi] = w;
+    });
+    __syncthreads();
+    // step 3: (m1, m2) = (lo, hi); the row is this thread's alone, read and written back
+    sfor<0, 8>([&](auto ic) { v[decltype(ic)::value] = S2[lo * RS + 8 * hi + decltype(ic)::value]; });
+    transform<8, -1>(v);
+    const double unit = 2.0 * kPi / (L * p.hk) / L;
+    sfor<0, 8>([&](auto mc) {
+        constexpr int m3 = decltype(mc)::value;
+        const int m = lo + 8 * hi + 64 * m3;
+        const double xi = m < L / 2 ? (double)m * unit : (m == L / 2 ? 0.0 : (double)(m - L) * unit);
+        v[m3] = {-xi * v[m3].im, xi * v[m3].re};
+    });
+    transform<8, +1>(v);
+    sfor<0, 8>([&](auto ic) { S2[lo * RS + 8 * hi + decltype(ic)::value] = v[decltype(ic)::value]; });
+    __syncthreads();
+    // step 2': (m1, n3) = (lo, hi)
+    sfor<0, 8>([&](auto mc) {
+        constexpr int m2 = decltype(mc)::value;
+        const cd x = S2[lo * RS + 8 * m2 + hi];
+        v[m2] = m2 > 0 ? cmul(x, tw[(8 * hi * m2) & (L - 1)]) : x;
+    });
+    transform<8, +1>(v);
+    sfor<0, 8>([&](auto ic) { S1[lo * RS + 8 * hi + decltype(ic)::value] = v[decltype(ic)::value]; });
+    __syncthreads();
+    // step 1': (n2, n3) = (lo, hi); d_k y at rows 64 n1 + 8 n2 + n3
+    sfor<0, 8>([&](auto mc) {
+        constexpr int m1 = decltype(mc)::value;
+        const cd x = S1[m1 * RS + 8 * hi + lo];
+        v[m1] = m1 > 0 ? cmul(x, tw[((8 * lo + hi) * m1) & (L - 1)]) : x;
+    });
+    transform<8, +1>(v);
+    const double fa = p.omega * (p.x_lo + xa * p.hx), fb = p.omega * (p.x_lo + xb * p.hx);
+    sfor<0, 8>([&](auto ic) {
+        constexpr int n1 = decltype(ic)::value;
+        const long long row = (long long)(64 * n1 + 8 * lo + hi) * p.nx;
+        if constexpr (MODE == 0) {
+            out[row + xa] = fa * v[n1].re;
+            if (has_b) out[row + xb] = fb * v[n1].im;
+        } else {
+            out[row + xa] = fma(h, fa * v[n1].re, keep[n1].re);
+            if (has_b) out[row + xb] = fma(h, fb * v[n1].im, keep[n1].im);
+        }
+    });
+}
+
 // mode 0: dst = a + c b;  mode 1: dst = a + c (b + y)
 __global__ __launch_bounds__(256) void k_ho_combine(double* __restrict__ dst, const double* __restrict__ a,
                                                    const double* __restrict__ b, const double* __restrict__ y,
@@ -384,7 +484,14 @@ static void launch_dk(int nk, int mode, const double* a, const double* b, double
     case 64: launch_dk_t<8, 8>(mode, a, b, out, tw, p, s); break;
     case 128: launch_dk_t<8, 16>(mode, a, b, out, tw, p, s); break;
     case 256: launch_dk_t<16, 16>(mode, a, b, out, tw, p, s); break;
-    case 512: launch_dk_t<16, 32>(mode, a, b, out, tw, p, s); break;
+    case 512: {
+        const dim3 grid((unsigned)((p.nx + 1) / 2));
+        if (mode == 0)
+            hipLaunchKernelGGL(k_ho_dk512<0>, grid, dim3(64), 0, s, a, b, out, tw, p);
+        else
+            hipLaunchKernelGGL(k_ho_dk512<1>, grid, dim3(64), 0, s, a, b, out, tw, p);
+        break;
+    }
     default: launch_dk_t<32, 32>(mode, a, b, out, tw, p, s); break;
     }
 }

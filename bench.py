@@ -464,7 +464,7 @@ def bench_ho2d(args):
         "accuracy": {"eps_inf": err_inf, "eps_2": err_2, "mass_deviation": mass_dev, "t": steps * tau},
         "roofline": {"bound": "alu", "achieved": flops / total_s / 1e12, "peak": 78.6, "unit": "TFLOP/s",
                      "frac": flops / total_s / 1e12 / 78.6, "traffic": None,
-                     "kernel": "whole step (k_ho_dk twice on 61 one-wave blocks, k_ho_advect once on 512 blocks); "
+                     "kernel": "whole step (k_ho_dk512 twice on 121 one-wave blocks, k_ho_advect once on 512 blocks); "
                                "the 1 MB working set stays in cache and each launch is a short dependent chain, so "
                                "the step is bound by latency, far from either roofline",
                      "flop_count": "per step: 2 x (nx+1)/2 x (10 nk log2 nk + 6 nk) for the derivatives plus "

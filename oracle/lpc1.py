@@ -10,8 +10,11 @@ Sec. 4) summed over the nuclei.
 TEST INFRASTRUCTURE, NOT PRODUCT CODE; it shares no code with the HIP library.  Pinned
 in ``tests/test_oracle_lpc1.py``: with no nuclei (Theta = 0) a step is exactly the
 characteristic step; as tau -> 0, (step - characteristic step)/tau tends to Theta[f]
-at first order in tau (which fixes the tau and tau/2 coefficients); the step is linear.
-The component operators carry their own pins.
+at first order in tau (which fixes the tau and tau/2 coefficients); the step is linear;
+and ``lpc1_step`` with exact linear operators in place of A_tau and Theta (the flow of
+a linear system, where e^{tau(D + T)} is the exact solution) converges at second order
+in tau, which a corrector that reuses Theta[f^n] o A_tau for Theta[f~], or a predictor
+without its tau term, does not.  The component operators carry their own pins.
 """
 from __future__ import annotations
 
@@ -42,12 +45,20 @@ def advect(f, grid, patch, ghost, tau):
     return oracle.advect6d(f, grid.nx, grid.hx, grid.nk, grid.k_lo, grid.hk, P, ghost, tau, 1)
 
 
+def lpc1_step(f, A, Th, tau):
+    """One LPC1 step (Sec. 2.2) with the characteristic step A(g) = g o A_tau and the
+    operator Th(g) = Theta[g] given as callables."""
+    th = Th(f)
+    af = A(f)
+    ath = A(th)
+    ft = af + tau * ath                                  # predictor
+    return af + 0.5 * tau * Th(ft) + 0.5 * tau * ath     # corrector
+
+
 def lpc1(f, grid, patch, ghost, tau, nsteps, nuclei, charges, direct=True):
     f = np.asarray(f, dtype=np.float64)
+    A = lambda g: advect(g, grid, patch, ghost, tau)
+    Th = lambda g: theta_field(g, grid, nuclei, charges, direct)
     for _ in range(nsteps):
-        th = theta_field(f, grid, nuclei, charges, direct)
-        af = advect(f, grid, patch, ghost, tau)
-        ath = advect(th, grid, patch, ghost, tau)
-        ft = af + tau * ath
-        f = af + 0.5 * tau * theta_field(ft, grid, nuclei, charges, direct) + 0.5 * tau * ath
+        f = lpc1_step(f, A, Th, tau)
     return f

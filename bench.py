@@ -1,30 +1,34 @@
 """Benchmark of the characteristic (spatial-advection) step on one MI355X.
 
-Workload: 32^3 x-nodes on [-12,12)^3 times 16^3 k-nodes on [-4,4)^3 (134,217,728
-phase-space points), patches of 8 cells, ghost width 6, dt = 0.02, seeded 4-packet
-Gaussian mixture, FP32 storage and arithmetic.  A step is one pass of the whole hot
-path: the x1, x2 and x3 sweeps of every point.
+Default workload (the largest single-GPU configuration): 64^3 x-nodes on [-16,16)^3
+times 32^3 k-nodes on [-4,4)^3 (8,589,934,592 phase-space points, 34 GB in FP32), one
+GPU's share of the paper's 6-D grids; patches of 16 cells, ghost width 8, dt = 0.02,
+seeded 8-packet Gaussian mixture, FP32 storage and arithmetic, FP64 mass and L2
+recorded after every step.  A step is one pass of the whole hot path: the x1, x2 and
+x3 sweeps of every point.  The x-cube does not fit in LDS, so the SLAB schedule runs:
+a call of K steps alternates the sweep order between steps and takes K + 1 passes
+over the field (one read and one write each), i.e. close to the method's 8 bytes per
+point-update.
 
 The field is resident in HBM before timing starts.  Before the W warmup steps the GPU
 is brought to its steady state by about 0.4 s of the same kernels on a scratch copy
-of the field (settle_steps; an idle device runs its first tens of milliseconds of
-this kernel up to 10 % slower, and plain copies do not remove that).  The K timed
-steps are one library call (K graph replays back to back on the library's stream)
-between two HIP events; value, ms_per_step and the mean duration of the dominant
-kernel (one kernel per step under the cube schedule) come from that interval.  A
-separate latency pass of L steps, with a HIP event recorded after every step, gives
-the per-step latency distribution (p50/p99).  Beside it: the plain
-FP64 form (three launches per step, eager) and the FP64 CPU oracle timed on a bounded
-sample of k-points (cpu_baseline), whose result at those k-points also gives the
-error of the timed GPU run.
+of the field (settle_steps).  The K timed steps are one library call (graph replays
+back to back on the library's stream) between two HIP events; value, ms_per_step and
+the roofline come from that interval.  A separate latency pass of L one-step calls,
+with a HIP event recorded after each, gives the latency of an isolated step
+(p50/p99).  Beside it: the plain FP64 form on the same grid (three launches per step,
+eager) and the FP64 CPU oracle timed on a bounded sample of k-points (cpu_baseline),
+whose result at those k-points also gives the error of the timed GPU run.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Other workloads (one JSON line each): --workload C3 (48^3 x 24^3, autotuned patch /
-ghost / schedule, FP64 mass and L2 recorded every step), --workload C4 (64^3 x 32^3,
-one GPU's share of a paper-scale grid, 34 GB per copy), --workload serving (200
-Poisson-arriving requests of mixed grids under a 200 GB HBM budget, continuous
-batching; p50/p99 step latency and aggregate point-updates/s).
+Other workloads (one JSON line each): --workload C2 (32^3 x 16^3, 134M points, the
+x-cube in LDS: one launch per step; the 537 MB field is partly served by the 256 MB
+memory-side cache), --workload C3 (48^3 x 24^3, autotuned patch / ghost / schedule),
+--workload serving (200 Poisson-arriving requests of mixed grids under a 200 GB HBM
+budget, continuous batching; p50/p99 step latency and aggregate point-updates/s),
+--workload theta / lpc1 / ho2d (the next rows: Theta_V, the LPC1 step, the 2-D
+harmonic oscillator).
 """
 import argparse
 import hashlib
@@ -68,13 +72,17 @@ def measured_traffic(kernel: str, workload: str, shape=None):
     return e.get("hbm_bytes_per_launch")
 
 
-def step_traffic(sched: str, workload: str, shape=None):
-    """Measured HBM bytes of one step: the cube kernel, or the slab + pencil pair."""
+def step_traffic(sched: str, workload: str, shape=None, steps: int = 0):
+    """Measured HBM bytes per step: the cube kernel; for the paired SLAB schedule the
+    K + 1 passes of a K-step call (slab x2x1x1x2 and pencil x3x3 alternate) per step;
+    None when no current counter run covers the kernels."""
     if sched == "cube":
         return measured_traffic("k_cube", workload, shape)
     if sched == "slab":
         a, b = measured_traffic("k_slab", workload, shape), measured_traffic("k_pencil", workload, shape)
-        return None if a is None or b is None else a + b
+        if a is None or b is None:
+            return None
+        return (a + b) / 2.0 * (steps + 1) / steps if steps else (a + b) / 2.0
     return None
 
 
@@ -202,7 +210,7 @@ def bench_large(args, name):
     f = torch.empty(g.shape(), dtype=torch.float32, device=dev)
     coef, gx, gk = inputs.packet_factors(g, w.packets)
     inputs.fill_separable(f, coef, gx, gk)
-    kidx = inputs.k_sample(g, args.cpu_kpoints / g.nkpts, 40)
+    kidx = inputs.k_sample(g, (args.cpu_kpoints or 96) / g.nkpts, 40)
     start = np.stack([f[i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in kidx])
     steps = args.steps
     lat = min(steps, args.latency_steps)
@@ -220,8 +228,25 @@ def bench_large(args, name):
     del f
     torch.cuda.empty_cache()
     value = g.points * steps / total_s
-    bpp = 8.0 if sched == "cube" else (16.0 if sched == "slab" else 24.0)
-    achieved = bpp * g.points / (total_s / steps) / 1e9
+    # the method's bytes: one FP32 read and one write of every point per step
+    achieved = 8.0 * g.points / (total_s / steps) / 1e9
+    sched_bpp = 8.0 if sched == "cube" else (8.0 * (steps + 1) / steps if sched == "slab" else 24.0)
+
+    # ---- plain FP64 one-job form on the same grid ---------------------------------
+    fp64 = None
+    if not args.no_fp64:
+        f64 = torch.empty(g.shape(), dtype=torch.float64, device=dev)
+        inputs.fill_separable(f64, *inputs.packet_factors(g, w.packets))
+        adv64 = chasm.Advect(f64, g, w.patch, w.ghost, w.dt, schedule="plain", stream=stream)
+        adv64.step(1)
+        n64 = max(2, min(args.fp64_steps, 10))
+        t64 = time_steps(adv64, torch, n64, stream)
+        adv64.close()
+        del f64
+        torch.cuda.empty_cache()
+        fp64 = {"value": g.points * n64 / t64, "unit": "point-updates/s", "ms_per_step": t64 * 1e3 / n64,
+                "steps": n64, "schedule": "plain (3 launches/step, eager)", "alg_bytes_per_point_update": 48}
+
     cpu = err = None
     if not args.no_cpu:
         nst = min(nall, args.cpu_steps) if args.cpu_steps else nall
@@ -229,22 +254,27 @@ def bench_large(args, name):
         if nst == nall:
             err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
     m0 = hist[0, 0, 0]
+    kern = {"cube": "k_cube", "slab": "k_slab (x2 x1 | x1 x2) and k_pencil (x3 | x3), alternating",
+            "plain": "k_slab (x1), k_pencil (x2), k_pencil (x3)"}[sched]
     return {
         "metric": METRIC, "value": value, "unit": "point-updates/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": total_s * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded Gaussian-packet mixture, generated on the GPU)",
-        "config": {"workload": f"{w.name}: {g.nx[0]}^3 x by {g.nk[0]}^3 k, {g.points} points, patch {w.patch[0]}, "
+        "config": {"workload": f"{w.name}: {g.nx[0]}^3 x [{g.x_lo[0]:g},{g.x_hi[0]:g})^3 by {g.nk[0]}^3 k "
+                               f"[{g.k_lo[0]:g},{g.k_hi[0]:g})^3, {g.points} points, patch {w.patch[0]}, "
                                f"ghost {w.ghost}, dt {w.dt}, FP32, one job, FP64 mass/L2 every step",
                    "schedule": sched, "graph": True, "out_of_place": oop},
         "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
                             "mean": float(per.mean()), "steps": lat,
-                            "pass": "separate, after the timed steps, one event per step"},
+                            "pass": "separate, after the timed steps: one-step calls, an event after each"},
         "settle_steps": settled, "steps_total": nall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": step_traffic(sched, name, (g.nx[0], w.patch[0], w.ghost)),
-                     "kernel": "whole step (" + ("k_cube" if sched == "cube" else "k_slab + k_pencil") + ")",
-                     "alg_bytes_per_point_update": bpp, "measured_copy_GBs": copy_gbs,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": step_traffic(sched, name, (g.nx[0], w.patch[0], w.ghost), steps),
+                     "kernel": "whole step: " + kern, "alg_bytes_per_point_update": 8.0,
+                     "schedule_bytes_per_point_update": sched_bpp, "measured_copy_GBs": copy_gbs,
                      "frac_of_copy": achieved / copy_gbs},
+        "fp64_plain": fp64, "fp32_vs_fp64_plain": None if fp64 is None else value / fp64["value"],
         "mass_drift": float(abs(hist[-1, 0, 0] - m0) / abs(m0)), "l2_last": float(hist[-1, 0, 1]),
         "autotune": tuning, "err_vs_oracle": err, "cpu_baseline": cpu,
     }
@@ -479,12 +509,13 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--fp64-steps", type=int, default=20)
-    ap.add_argument("--cpu-kpoints", type=int, default=24)
+    ap.add_argument("--cpu-kpoints", type=int, default=0,
+                    help="k-points of the oracle sample (default: 24 for C2, 96 for C3 and C4)")
     ap.add_argument("--latency-steps", type=int, default=50,
                     help="steps of the separate per-step latency pass (at most --steps)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "serving", "theta", "lpc1", "ho2d"])
+    ap.add_argument("--workload", default="C4", choices=["C2", "C3", "C4", "serving", "theta", "lpc1", "ho2d"])
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -535,7 +566,7 @@ def main():
     f = torch.empty(g.shape(), dtype=torch.float32, device=dev)
     coef, gx, gk = inputs.packet_factors(g, w.packets)
     inputs.fill_separable(f, coef, gx, gk)
-    kidx = inputs.k_sample(g, args.cpu_kpoints / g.nkpts, 40)
+    kidx = inputs.k_sample(g, (args.cpu_kpoints or 24) / g.nkpts, 40)
     start_cubes = np.stack([f[i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in kidx])
     torch.cuda.synchronize()
     adv = chasm.Advect(f, g, w.patch, w.ghost, w.dt, graph=True, stream=stream)

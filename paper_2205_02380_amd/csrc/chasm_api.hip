@@ -148,6 +148,10 @@ struct chasm_advect_s {
     hipGraphExec_t gexeck = nullptr;
     hipGraph_t graph_r = nullptr;    // one CUBE step visiting the items last to first
     hipGraphExec_t gexec_r = nullptr;
+    // SLAB pass sequences (see SlabSeq): one step, head, one and four middle units,
+    // the two tails
+    hipGraph_t sgraph[6] = {};
+    hipGraphExec_t sgexec[6] = {};
     bool rev_next = false;           // the next CUBE step of chasm_advect_step visits in reverse
     hipStream_t cap_stream = nullptr;
     bool poisoned = false;
@@ -225,11 +229,14 @@ static int resolve_schedule(const chasm_advect_desc* d, const KernelSet* ks)
     return ks->cube ? CHASM_SCHED_CUBE : CHASM_SCHED_SLAB;
 }
 
-// Rows of FP64 partials per batch member written by a step's fused reduction.
+// Rows of FP64 partials per batch member that a fused reduction of schedule sched can
+// write (the largest over the passes that end a step).
 static long long step_partial_rows(const chasm_advect_desc* d, const KernelSet* ks, int sched)
 {
     const long long nkp = (long long)d->nk[0] * d->nk[1] * d->nk[2];
-    return nkp * (sched == CHASM_SCHED_CUBE ? ks->cube_rows : ks->pencil_rows);
+    if (sched == CHASM_SCHED_CUBE) return nkp * ks->cube_rows;
+    if (sched == CHASM_SCHED_SLAB) return nkp * std::max(ks->pencil_rows, ks->slab_rows);
+    return nkp * ks->pencil_rows;
 }
 
 // Device table block: per axis the FP64 shift weights, their FP32 mirror and the
@@ -277,7 +284,8 @@ static size_t field_bytes(const chasm_advect_desc* d)
 static size_t workspace_bytes(const chasm_advect_desc* d, const KernelSet* ks, int sched, size_t table_bytes)
 {
     const long long nkp = (long long)d->nk[0] * d->nk[1] * d->nk[2];
-    const long long rows = std::max(step_partial_rows(d, ks, sched), nkp) * d->nbatch;
+    const bool red = (d->flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
+    const long long rows = (red ? std::max(step_partial_rows(d, ks, sched), nkp) : nkp) * d->nbatch;
     const int cap = d->history_cap > 0 ? d->history_cap : 1024;
     size_t b = table_bytes + 256;
     b += (size_t)rows * NRED * sizeof(double) + 256;
@@ -288,26 +296,52 @@ static size_t workspace_bytes(const chasm_advect_desc* d, const KernelSet* ks, i
     return b;
 }
 
-// Launch one step of schedule sched on stream s; pw[p] is the work list of the step's
-// p-th launch (CUBE uses pw[0], SLAB pw[0..1], PLAIN pw[0..2]).
+// Launch one step of schedule sched (CUBE or PLAIN) on stream s; pw[p] is the work
+// list of the step's p-th launch (CUBE uses pw[0], PLAIN pw[0..2]).
 static hipError_t launch_step(const KernelSet* ks, int sched, const Work* const pw[3], double* part, hipStream_t s)
 {
     hipError_t e = hipSuccess;
-    switch (sched) {
-    case CHASM_SCHED_CUBE:
+    if (sched == CHASM_SCHED_CUBE) {
         e = ks->cube(*pw[0], part, s);
-        break;
-    case CHASM_SCHED_SLAB:
-        e = ks->slab_x1x2(*pw[0], nullptr, s);
-        if (e == hipSuccess) e = ks->pencil_x3(*pw[1], part, s);
-        break;
-    default:
-        e = ks->slab_x1(*pw[0], nullptr, s);
+    } else {
+        e = ks->slab[SLAB_X1](*pw[0], nullptr, s);
         if (e == hipSuccess) e = ks->pencil_x2(*pw[1], nullptr, s);
         if (e == hipSuccess) e = ks->pencil_x3(*pw[2], part, s);
-        break;
     }
     return e;
+}
+
+// ---------------------------------------------------------------------------
+// SLAB schedule.  A call of K steps alternates the sweep order between steps (x1 x2 x3,
+// then x3 x2 x1, ...; the axis operators commute, see SlabMode), so it runs K + 1
+// passes: pass r is
+//   r = 0                      slab  x1 x2
+//   r odd,  r < K              pencil x3 x3   (ends step r)
+//   r even, 0 < r < K          slab  x2 x1 | x1 x2   (ends step r)
+//   r = K odd                  pencil x3      (ends step K)
+//   r = K even                 slab  x2 x1    (ends step K)
+// Every pass but the first ends exactly one step, and a call always ends with the
+// field after its last step.
+enum PassKind { PASS_SLAB_A = 0, PASS_SLAB_B, PASS_SLAB_C, PASS_PENCIL_1, PASS_PENCIL_2 };
+
+static int slab_pass_kind(int r, int K)
+{
+    if (r == 0) return PASS_SLAB_A;
+    if (r % 2) return r == K ? PASS_PENCIL_1 : PASS_PENCIL_2;
+    return r == K ? PASS_SLAB_C : PASS_SLAB_B;
+}
+
+static bool pass_is_slab(int kind) { return kind <= PASS_SLAB_C; }
+
+static hipError_t launch_pass(const KernelSet* ks, int kind, const Work& w, double* part, hipStream_t s)
+{
+    switch (kind) {
+    case PASS_SLAB_A: return ks->slab[SLAB_X1X2](w, nullptr, s);
+    case PASS_SLAB_B: return ks->slab[SLAB_X2X1X1X2](w, part, s);
+    case PASS_SLAB_C: return ks->slab[SLAB_X2X1](w, part, s);
+    case PASS_PENCIL_1: return ks->pencil_x3(w, part, s);
+    default: return ks->pencil_x3x3(w, part, s);
+    }
 }
 
 // The work lists of one step of a handle.  In place, every launch reads and writes f.
@@ -319,14 +353,20 @@ static void step_passes(const chasm_advect_s* h, const Work* pw[3])
 {
     if (!h->stage || h->schedule == CHASM_SCHED_CUBE) {
         pw[0] = pw[1] = pw[2] = &h->work;
-    } else if (h->schedule == CHASM_SCHED_SLAB) {
-        pw[0] = &h->w_fs;
-        pw[1] = pw[2] = &h->w_sf;
     } else {
         pw[0] = &h->w_fs;
         pw[1] = &h->w_ss;
         pw[2] = &h->w_sf;
     }
+}
+
+// Work list of a SLAB pass.  Out of place, slab passes that continue into a pencil read
+// f and write the stage field and pencils read the stage field and write f; the closing
+// x2 x1 slab runs in place on f.
+static const Work* slab_pass_work(const chasm_advect_s* h, int kind)
+{
+    if (!h->stage || kind == PASS_SLAB_C) return &h->work;
+    return pass_is_slab(kind) ? &h->w_fs : &h->w_sf;
 }
 
 // Issue one step's kernels of one handle on stream s.
@@ -349,8 +389,14 @@ static hipError_t launch_finalize(chasm_advect_s* h, long long rows, bool record
 // rev: a CUBE step visits the items last to first.  chasm_advect_step alternates the
 // order from step to step, so the items a step stores last are the first ones the next
 // step loads, while they may still sit in the memory-side cache.
+static hipError_t issue_passes(chasm_advect_t h, hipStream_t s, const int* kinds, int n);
+
 static hipError_t issue_step(chasm_advect_t h, hipStream_t s, bool rev = false)
 {
+    if (h->schedule == CHASM_SCHED_SLAB) {
+        const int one[2] = {PASS_SLAB_A, PASS_PENCIL_1};
+        return issue_passes(h, s, one, 2);
+    }
     const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
     double* part = red ? h->partials : nullptr;
     const Work* pw[3];
@@ -363,6 +409,62 @@ static hipError_t issue_step(chasm_advect_t h, hipStream_t s, bool rev = false)
     }
     hipError_t e = launch_step(h->ks, h->schedule, pw, part, s);
     if (e == hipSuccess && red) e = launch_finalize(h, h->partial_rows, true, s);
+    return e;
+}
+
+// Issue SLAB passes of the given kinds on stream s, each pass that ends a step followed
+// by its reduction when the handle records per-step diagnostics.
+static hipError_t issue_passes(chasm_advect_t h, hipStream_t s, const int* kinds, int n)
+{
+    const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
+    const long long nkp = (long long)h->desc.nk[0] * h->desc.nk[1] * h->desc.nk[2];
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        const int kind = kinds[i];
+        const bool ends = red && kind != PASS_SLAB_A;
+        e = launch_pass(h->ks, kind, *slab_pass_work(h, kind), ends ? h->partials : nullptr, s);
+        if (e == hipSuccess && ends)
+            e = launch_finalize(h, nkp * (pass_is_slab(kind) ? h->ks->slab_rows : h->ks->pencil_rows), true, s);
+    }
+    return e;
+}
+
+// SLAB graph slots and their pass lists.
+enum { SG_ONE = 0, SG_HEAD, SG_MID1, SG_MID4, SG_TAIL_EVEN, SG_TAIL_ODD, SG_COUNT };
+static int slab_graph_passes(int g, int* kinds)
+{
+    switch (g) {
+    case SG_ONE: kinds[0] = PASS_SLAB_A; kinds[1] = PASS_PENCIL_1; return 2;
+    case SG_HEAD: kinds[0] = PASS_SLAB_A; kinds[1] = PASS_PENCIL_2; return 2;
+    case SG_MID1: kinds[0] = PASS_SLAB_B; kinds[1] = PASS_PENCIL_2; return 2;
+    case SG_MID4:
+        for (int i = 0; i < 4; ++i) {
+            kinds[2 * i] = PASS_SLAB_B;
+            kinds[2 * i + 1] = PASS_PENCIL_2;
+        }
+        return 8;
+    case SG_TAIL_EVEN: kinds[0] = PASS_SLAB_C; return 1;
+    default: kinds[0] = PASS_SLAB_B; kinds[1] = PASS_PENCIL_1; return 2;
+    }
+}
+
+// K steps of a SLAB handle: K + 1 passes (slab_pass_kind), as graph replays when the
+// handle has them.
+static hipError_t slab_steps(chasm_advect_t h, hipStream_t s, int K)
+{
+    if (K <= 0) return hipSuccess;
+    auto run = [&](int g) {
+        if (h->sgexec[g]) return hipGraphLaunch(h->sgexec[g], s);
+        int kinds[8];
+        const int n = slab_graph_passes(g, kinds);
+        return issue_passes(h, s, kinds, n);
+    };
+    if (K == 1) return run(SG_ONE);
+    hipError_t e = run(SG_HEAD);
+    const int mid = (K % 2 == 0) ? (K - 2) / 2 : (K - 3) / 2;
+    for (int i = 0; i < mid / 4 && e == hipSuccess; ++i) e = run(SG_MID4);
+    for (int i = 0; i < mid % 4 && e == hipSuccess; ++i) e = run(SG_MID1);
+    if (e == hipSuccess) e = run(K % 2 == 0 ? SG_TAIL_EVEN : SG_TAIL_ODD);
     return e;
 }
 
@@ -448,7 +550,10 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
 
     const long long nkp = (long long)desc->nk[0] * desc->nk[1] * desc->nk[2];
     h->partial_rows = step_partial_rows(desc, ks, h->schedule);
-    const long long rows = std::max(h->partial_rows, nkp) * desc->nbatch;
+    // partial rows: one per item for diagnostics of the current field, and per block of
+    // the passes that end a step when those reduce
+    const bool red = (desc->flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
+    const long long rows = (red ? std::max(h->partial_rows, nkp) : nkp) * desc->nbatch;
     if (hipMalloc((void**)&h->partials, (size_t)rows * NRED * sizeof(double)) != hipSuccess)
         return bail(CHASM_ENOMEM, "hipMalloc(partials) failed");
     if (hipMalloc((void**)&h->fold, (size_t)desc->nbatch * FOLD_CHUNKS * NRED * sizeof(double)) != hipSuccess)
@@ -510,6 +615,21 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
             const hipError_t ee = hipStreamEndCapture(h->cap_stream, g);
             return ce == hipSuccess && ee == hipSuccess && hipGraphInstantiate(x, *g, nullptr, nullptr, 0) == hipSuccess;
         };
+        if (h->schedule == CHASM_SCHED_SLAB) {
+            for (int g = 0; g < SG_COUNT; ++g) {
+                int kinds[8];
+                const int n = slab_graph_passes(g, kinds);
+                if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                    return bail(CHASM_EDEVICE, "hipStreamBeginCapture failed");
+                const hipError_t ce = issue_passes(h, h->cap_stream, kinds, n);
+                const hipError_t ee = hipStreamEndCapture(h->cap_stream, &h->sgraph[g]);
+                if (ce != hipSuccess || ee != hipSuccess ||
+                    hipGraphInstantiate(&h->sgexec[g], h->sgraph[g], nullptr, nullptr, 0) != hipSuccess)
+                    return bail(CHASM_EDEVICE, "pass-sequence capture failed");
+            }
+            *out = h;
+            return CHASM_OK;
+        }
         if (!capture(1, &h->graph, &h->gexec)) return bail(CHASM_EDEVICE, "step capture failed");
         if (h->schedule == CHASM_SCHED_CUBE) {   // the reversed single step
             if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -532,6 +652,11 @@ chasm_status chasm_advect_step(chasm_advect_t h, int32_t nsteps)
     if (!h) return fail(CHASM_EINVAL, "handle is NULL");
     if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
     if (nsteps < 0) return fail(CHASM_EINVAL, "nsteps must be >= 0");
+    if (h->schedule == CHASM_SCHED_SLAB) {
+        hipError_t e = slab_steps(h, h->stream, nsteps);
+        if (e != hipSuccess) return hip_fail(h, e, "step launch");
+        return CHASM_OK;
+    }
     const bool cube = h->schedule == CHASM_SCHED_CUBE;
     // One step in the current visiting order; the order alternates for CUBE.
     auto single = [&]() {
@@ -567,7 +692,6 @@ chasm_status chasm_advect_step(chasm_advect_t h, int32_t nsteps)
 chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const int32_t* nsteps)
 {
     if (n < 0 || (n > 0 && (!hs || !nsteps))) return fail(CHASM_EINVAL, "bad handle list");
-    int32_t most = 0;
     for (int32_t i = 0; i < n; ++i) {
         if (!hs[i]) return fail(CHASM_EINVAL, "NULL handle in list");
         if (hs[i]->poisoned) return fail(CHASM_ESTATE, "a handle in the list is poisoned");
@@ -575,39 +699,60 @@ chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const i
         if (hs[i]->stream != hs[0]->stream) return fail(CHASM_EINVAL, "all handles must share one stream");
         for (int32_t j = 0; j < i; ++j)
             if (hs[j] == hs[i]) return fail(CHASM_EINVAL, "a handle appears twice in the list");
-        most = std::max(most, nsteps[i]);
     }
     hipStream_t s = n > 0 ? hs[0]->stream : nullptr;
-    // Step-major: every job advances one step before any job takes the next.  Handles
-    // with the same kernels and schedule share one launch per sweep (work lists of at
-    // most kMaxJobs jobs); handles that record per-step diagnostics step on their own.
-    std::vector<chasm_advect_t> live;
-    for (int32_t st = 0; st < most; ++st) {
+    // Handles that record per-step diagnostics run their call on their own, exactly as
+    // chasm_advect_step does.
+    for (int32_t i = 0; i < n; ++i)
+        if (hs[i]->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) {
+            const chasm_status st = chasm_advect_step(hs[i], nsteps[i]);
+            if (st != CHASM_OK) return st;
+        }
+    // The others advance round by round: round r is step r of a CUBE or PLAIN handle and
+    // pass r of a SLAB handle's K + 1 passes (slab_pass_kind), so every job progresses
+    // together.  Handles with the same kernels, schedule and pass share one launch (work
+    // lists of at most kMaxJobs jobs).
+    constexpr int kStep = -1;
+    auto kind_at = [&](int32_t i, int32_t r) -> int {   // what round r runs for handle i (-2: nothing)
+        const int32_t K = nsteps[i];
+        if (hs[i]->schedule == CHASM_SCHED_SLAB) return (K > 0 && r <= K) ? slab_pass_kind(r, K) : -2;
+        return r < K ? kStep : -2;
+    };
+    int32_t rounds = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (!(hs[i]->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP))
+            rounds = std::max(rounds, hs[i]->schedule == CHASM_SCHED_SLAB && nsteps[i] > 0 ? nsteps[i] + 1 : nsteps[i]);
+    std::vector<int32_t> live;
+    std::vector<int> kinds;
+    for (int32_t r = 0; r < rounds; ++r) {
         live.clear();
-        for (int32_t i = 0; i < n; ++i)
-            if (st < nsteps[i]) live.push_back(hs[i]);
+        kinds.clear();
+        for (int32_t i = 0; i < n; ++i) {
+            if (hs[i]->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) continue;
+            const int k = kind_at(i, r);
+            if (k == -2) continue;
+            live.push_back(i);
+            kinds.push_back(k);
+        }
         std::vector<bool> done(live.size(), false);
         for (size_t a = 0; a < live.size(); ++a) {
             if (done[a]) continue;
-            chasm_advect_t h = live[a];
-            if (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) {
-                hipError_t e = h->gexec ? hipGraphLaunch(h->gexec, s) : issue_step(h, s);
-                if (e != hipSuccess) return hip_fail(h, e, "step launch");
-                done[a] = true;
-                continue;
-            }
-            // One work list per launch of the step; job j of list p is pass p of its
-            // handle (in place, or through that handle's stage field).
+            chasm_advect_t h = hs[live[a]];
+            const int kind = kinds[a];
+            // One work list per launch; job j of list p is launch p of its handle's step
+            // (in place, or through that handle's stage field).
             Work w[3] = {};
             for (size_t b = a; b < live.size() && w[0].njobs < kMaxJobs; ++b) {
-                chasm_advect_t o = live[b];
-                if (done[b] || o->ks != h->ks || o->schedule != h->schedule ||
-                    (o->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP))
-                    continue;
+                chasm_advect_t o = hs[live[b]];
+                if (done[b] || o->ks != h->ks || o->schedule != h->schedule || kinds[b] != kind) continue;
                 const long long items = o->work.jobs[0].nitems;
                 if (w[0].first[w[0].njobs] + items > (1LL << 24)) break;   // keep launch grids small
                 const Work* pw[3];
-                step_passes(o, pw);
+                if (kind == kStep) {
+                    step_passes(o, pw);
+                } else {
+                    pw[0] = pw[1] = pw[2] = slab_pass_work(o, kind);
+                }
                 for (int p = 0; p < 3; ++p) {
                     w[p].jobs[w[p].njobs] = pw[p]->jobs[0];
                     w[p].first[w[p].njobs + 1] = w[p].first[w[p].njobs] + items;
@@ -615,14 +760,20 @@ chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const i
                 }
                 done[b] = true;
             }
+            hipError_t e = hipSuccess;
             if (w[0].njobs == 0) {   // a single job larger than the per-launch bound
-                hipError_t e = issue_step(h, s);
-                if (e != hipSuccess) return hip_fail(h, e, "step launch");
+                if (kind == kStep) {
+                    e = issue_step(h, s);
+                } else {
+                    e = launch_pass(h->ks, kind, *slab_pass_work(h, kind), nullptr, s);
+                }
                 done[a] = true;
-                continue;
+            } else if (kind == kStep) {
+                const Work* pw[3] = {&w[0], &w[1], &w[2]};
+                e = launch_step(h->ks, h->schedule, pw, nullptr, s);
+            } else {
+                e = launch_pass(h->ks, kind, w[0], nullptr, s);
             }
-            const Work* pw[3] = {&w[0], &w[1], &w[2]};
-            hipError_t e = launch_step(h->ks, h->schedule, pw, nullptr, s);
             if (e != hipSuccess) return hip_fail(h, e, "batched step launch");
         }
     }
@@ -742,6 +893,10 @@ chasm_status chasm_advect_destroy(chasm_advect_t h)
     if (h->graphk) hipGraphDestroy(h->graphk);
     if (h->gexec_r) hipGraphExecDestroy(h->gexec_r);
     if (h->graph_r) hipGraphDestroy(h->graph_r);
+    for (int g = 0; g < SG_COUNT; ++g) {
+        if (h->sgexec[g]) hipGraphExecDestroy(h->sgexec[g]);
+        if (h->sgraph[g]) hipGraphDestroy(h->sgraph[g]);
+    }
     if (h->stage) hipFree(h->stage);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->tables) hipFree(h->tables);

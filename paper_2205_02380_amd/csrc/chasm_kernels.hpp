@@ -12,11 +12,11 @@
 //   k_cube    all three sweeps of one item with the whole x-cube in LDS
 //             (N^2 (N+1) values, rows padded to N+1 so x1-, x2- and x3-lines are
 //             bank-conflict free): 8 B/point-update in FP32.
-//   k_slab    x1 sweep, optionally followed by the x2 sweep, on S x3-slabs (N x N)
-//             held in LDS; persistent, with the next unit's loads in flight.
-//   k_pencil  x2 or x3 sweep; each lane holds one whole line in VGPRs, lanes of a
-//             wave hold neighbouring x1 columns, so every load and store of the
-//             wave is a contiguous run of x1.
+//   k_slab    x1 and x2 sweeps (see SlabMode) on S x3-slabs (N x N) held in LDS;
+//             persistent, with the next unit's loads in flight.
+//   k_pencil  one or two x2 or x3 sweeps; each lane holds one whole line in VGPRs,
+//             lanes of a wave hold neighbouring x1 columns, so every load and store
+//             of the wave is a contiguous run of x1.
 //   k_reduce_field, k_finalize: FP64 diagnostics (mass, L2, first moments).
 // Reductions can be fused into the last sweep of a step; every block writes its
 // own FP64 partials and k_finalize sums them in a fixed order (deterministic).
@@ -406,22 +406,38 @@ __global__ __launch_bounds__(NT) void k_cube(const Work w, double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// S x3-slabs (N x N each) per block in LDS: x1 sweep, then (X2 = true) the x2 sweep
-// stored straight to global memory.  Block = S*N threads, one line each.
-template <typename T, int N, int M, int G, int CL, int S, bool X2>
-__global__ __launch_bounds__(S * N) void k_slab(const Work w)
+// Sweep sequences of k_slab (applied to every x3-slab of a unit, left to right):
+//   SLAB_X1        x1                 (first launch of the three-launch schedule)
+//   SLAB_X1X2      x1 x2              (first pass of a step)
+//   SLAB_X2X1X1X2  x2 x1 | x1 x2      (the end of one step and the start of the next)
+//   SLAB_X2X1      x2 x1              (the end of the last step of a call)
+// Consecutive steps of a multi-step call alternate the sweep order, x1 x2 x3 then
+// x3 x2 x1: the three axis operators act on different indices of the tensor-product
+// spline (eqs. 3.11-3.12) and commute exactly, so the order changes only the rounding.
+// Adjacent sweeps along the same axes then share a pass: K steps take K + 1 passes
+// (slab, pencil, slab, ...), one read and one write of the field per pass.
+enum SlabMode { SLAB_X1 = 0, SLAB_X1X2 = 1, SLAB_X2X1X1X2 = 2, SLAB_X2X1 = 3 };
+
+// S x3-slabs (N x N each) per block in LDS, block = S*N threads (one line each per
+// sweep).  Persistent over units of S consecutive slabs of one item.  PRE: the next
+// unit's 16-byte loads are in flight in VGPRs while this unit is swept and stored
+// (otherwise a unit is loaded when its turn comes, and other resident blocks hide the
+// latency).  Units are disjoint, so in place a prefetch never reads what another unit
+// writes.
+// RED: FP64 partials of the field after the sweep that completes a step (the first
+// x1 sweep of SLAB_X2X1X1X2, the x1 sweep of SLAB_X2X1), one row per unit.
+template <typename T, int N, int M, int G, int CL, int S, int MODE, bool PRE, bool RED>
+__global__ __launch_bounds__(S * N) void k_slab(const Work w, double* __restrict__ partials)
 {
     constexpr int PX = N + 1;
     constexpr int NT = S * N;
     constexpr int VW = Vec16<T>::n;
     constexpr int RV = S * N * N / VW / NT;        // 16-byte vectors per lane per unit
     static_assert(N % VW == 0 && N % S == 0 && (S * N * N / VW) % NT == 0, "bad slab shape");
+    static_assert(!RED || MODE == SLAB_X2X1X1X2 || MODE == SLAB_X2X1, "no step ends in this pass");
     using V = typename Vec16<T>::type;
     __shared__ T lds[S * N * PX];
 
-    // Persistent over units (S consecutive x3-slabs of one item); the next unit's loads
-    // are in flight in VGPRs while this unit is swept and stored.  Units are disjoint,
-    // so in place a prefetch never reads what another unit writes.
     constexpr int BPI = N / S;                     // units per item
     const long long units = w.first[w.njobs] * BPI;
     long long u = blockIdx.x;
@@ -434,8 +450,9 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
                                                   (long long)(uu % BPI) * S * N * N);
         static_for<0, RV>([&](auto qc) { pre[decltype(qc)::value] = src[decltype(qc)::value * NT + threadIdx.x]; });
     };
-    fetch(u);
+    if constexpr (PRE) fetch(u);
     for (;;) {
+        if constexpr (!PRE) fetch(u);
         static_for<0, RV>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             const int e = q * NT + threadIdx.x;
@@ -445,7 +462,9 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
         });
         __syncthreads();
         const long long next = u + gridDim.x;
-        if (next < units) fetch(next);
+        if constexpr (PRE) {
+            if (next < units) fetch(next);
+        }
 
         long long item;
         const JobDev& job = job_of(w, u / BPI, item);
@@ -453,20 +472,57 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
         int ik[3];
         item_k(job, item, ik);
         T* out_ptr = static_cast<T*>(job.out) + item * (long long)(N * N * N) + (long long)slab0 * N * N;
-        {
+        const int slab_t = threadIdx.x / N, col_t = threadIdx.x % N;
+        double s = 0.0, s2 = 0.0, sj = 0.0;        // partial sums of this thread's row (RED)
+        auto tally = [&](int j, T x) {
+            if constexpr (RED) {
+                const double y = (double)x;
+                s += y;
+                s2 = fma(y, y, s2);
+                sj = fma((double)j, y, sj);
+            }
+        };
+
+        if constexpr (MODE == SLAB_X2X1X1X2 || MODE == SLAB_X2X1) {
+            // x2 on the columns (x1 = col_t) of this thread's slab, in LDS
             int sigma;
-            const auto kc = axis_coef<T>(job, 0, ik[0], sigma);
-            const int base = threadIdx.x * PX;          // row (x2, slab) = (t % N, t / N)
+            const auto kc = axis_coef<T>(job, 1, ik[1], sigma);
+            T* col = lds + slab_t * N * PX + col_t;
             dispatch_sigma(sigma, [&](auto sc) {
                 T v[N];
 #pragma unroll
-                for (int i = 0; i < N; ++i) v[i] = lds[base + i];
-                advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { lds[base + j] = x; });
+                for (int i = 0; i < N; ++i) v[i] = col[i * PX];
+                advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { col[j * PX] = x; });
             });
+            __syncthreads();
+        }
+        {   // x1 on the rows (x2, slab) = (col_t, slab_t), once or (SLAB_X2X1X1X2) twice.
+            // The two x1 sweeps of SLAB_X2X1X1X2 run back to back through this thread's
+            // own LDS row (no other thread touches it, so no barrier between them), as a
+            // loop kept rolled so that the compiler never holds two lines at once.
+            int sigma;
+            const auto kc = axis_coef<T>(job, 0, ik[0], sigma);
+            T* row = lds + threadIdx.x * PX;
+            constexpr int NX1 = MODE == SLAB_X2X1X1X2 ? 2 : 1;
+#pragma unroll 1
+            for (int pass = 0; pass < NX1; ++pass) {
+                dispatch_sigma(sigma, [&](auto sc) {
+                    T v[N];
+#pragma unroll
+                    for (int i = 0; i < N; ++i) v[i] = row[i];
+                    advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { row[j] = x; });
+                });
+                if constexpr (RED) {
+                    if (pass == 0) {   // the step ends after the first x1 sweep
+#pragma unroll
+                        for (int i = 0; i < N; ++i) tally(i, row[i]);
+                    }
+                }
+            }
         }
         __syncthreads();
 
-        if (!X2) {
+        if constexpr (MODE == SLAB_X1 || MODE == SLAB_X2X1) {
             V* dst = reinterpret_cast<V*>(out_ptr);
 #pragma unroll
             for (int e = threadIdx.x; e < S * N * N / VW; e += NT) {
@@ -477,17 +533,22 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
                 dst[e] = x;
             }
         } else {
+            // x2 on the columns, stored straight to global memory
             int sigma;
             const auto kc = axis_coef<T>(job, 1, ik[1], sigma);
-            const int slab = threadIdx.x / N, col = threadIdx.x % N;
-            const int base = slab * N * PX + col;
-            T* out = out_ptr + slab * N * N + col;
+            const int base = slab_t * N * PX + col_t;
+            T* out = out_ptr + slab_t * N * N + col_t;
             dispatch_sigma(sigma, [&](auto sc) {
                 T v[N];
 #pragma unroll
                 for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
                 advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { out[j * N] = x; });
             });
+        }
+        if constexpr (RED) {
+            // this thread's row: x2 = col_t, x3 = slab0 + slab_t; sj carries the x1 index
+            double acc[5] = {s, s2, sj, (double)col_t * s, (double)(slab0 + slab_t) * s};
+            write_partials<NT>(acc, ik, partials + u * NRED);
         }
         if (next >= units) break;
         __syncthreads();   // the output phase has read the LDS before the next fill
@@ -497,11 +558,14 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w)
 
 // ---------------------------------------------------------------------------
 // One line per lane along axis AXIS (1: x2, 2: x3), NT lines per block; NT divides
-// N*N so a block never straddles two items.  Optional fused FP64 partials.
-template <typename T, int N, int M, int G, int CL, int NT, int AXIS, bool RED>
+// N*N so a block never straddles two items.  NSW sweeps along the axis (2: the x3
+// sweep that ends one step and the x3 sweep that starts the next, see SlabMode).
+// RED: FP64 partials of the field after the first sweep, one row per block.
+template <typename T, int N, int M, int G, int CL, int NT, int AXIS, int NSW, bool RED>
 __global__ __launch_bounds__(NT) void k_pencil(const Work w, double* __restrict__ partials)
 {
     static_assert((N * N) % NT == 0, "block must tile the lines of one item");
+    static_assert(NSW == 1 || NSW == 2, "one or two sweeps");
     constexpr int BPI = N * N / NT;
     long long item;
     const JobDev& job = job_of(w, blockIdx.x / BPI, item);
@@ -526,18 +590,43 @@ __global__ __launch_bounds__(NT) void k_pencil(const Work w, double* __restrict_
         v[i] = buf.load<T>(voff, i * sstride);
     });
     double s = 0.0, s2 = 0.0, sj = 0.0;
+    auto tally = [&](int j, T x) {
+        if constexpr (RED) {
+            const double y = (double)x;
+            s += y;
+            s2 = fma(y, y, s2);
+            sj = fma((double)j, y, sj);
+        }
+    };
+    auto store = [&](int j, T x) { obuf.store<T>(x, voff, j * sstride); };
     dispatch_sigma(sigma, [&](auto sc) {
         constexpr int SIG = decltype(sc)::value;
-        if constexpr (!RED) {
-            advect_line<T, N, M, G, CL, SIG>(v, kc, sigma, [&](int j, T x) { obuf.store<T>(x, voff, j * sstride); });
-        } else {
+        if constexpr (NSW == 1) {
             advect_line<T, N, M, G, CL, SIG>(v, kc, sigma, [&](int j, T x) {
-                obuf.store<T>(x, voff, j * sstride);
-                const double y = (double)x;
-                s += y;
-                s2 = fma(y, y, s2);
-                sj = fma((double)j, y, sj);
+                store(j, x);
+                tally(j, x);
             });
+        } else {
+            // The intermediate line stays in this lane's registers.  For SIG_ANY the
+            // first sweep's cell values go through the compile-time barrel shifter of
+            // store_cells, so no register array is ever indexed at run time (an FP32
+            // form that wrote y[j] at the runtime index j compiled to GPR-indexing mode
+            // and gave wrong values for those lines on gfx950; its FP64 twin did not).
+            T y[N];
+            if constexpr (SIG != SIG_ANY) {
+                advect_line<T, N, M, G, CL, SIG>(v, kc, sigma, [&](int j, T x) {
+                    y[j] = x;
+                    tally(j, x);
+                });
+            } else {
+                T cv[N + 7];
+                line_cells<T, N, M, G, CL>(v, cv, kc);
+                store_cells<T, N, SIG_ANY>(cv, sigma, [&](int j, T x) {
+                    y[j] = x;
+                    tally(j, x);
+                });
+            }
+            advect_line<T, N, M, G, CL, SIG>(y, kc, sigma, store);
         }
     });
     if constexpr (RED) {

@@ -21,6 +21,12 @@ struct Launch {
     static constexpr int slab_s = N == 8 ? 8 : (N == 16 ? 4 : (N == 24 ? 8 : (N == 32 ? 2 : (N == 48 ? 4 : 1))));
     // lines per pencil block: a multiple of 64 dividing N*N.
     static constexpr int pencil_nt = N == 8 ? 64 : (N == 24 ? 192 : 256);
+    // Slab passes keep the next unit's loads in flight in VGPRs (see k_slab) where a
+    // line is at most 256 bytes; SLAB_X2X1X1X2 (four sweeps per unit) trades that for
+    // occupancy: at N = 64 in FP32 it needs 156 VGPRs without the prefetch (three
+    // waves per SIMD), 221 with it.
+    static constexpr bool slab_pre = sizeof(T) * N <= 256;
+    static constexpr bool slab_pre_b = false;
     static constexpr int reduce_nt = 256;
 };
 
@@ -65,24 +71,31 @@ hipError_t launch_cube(const Work& w, double* partials, hipStream_t s)
     }
 }
 
-template <typename T, int N, int M, int G, int CL, bool X2>
-hipError_t launch_slab(const Work& w, double*, hipStream_t s)
+template <typename T, int N, int M, int G, int CL, int MODE>
+hipError_t launch_slab(const Work& w, double* partials, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     constexpr int S = Lc::slab_s;
-    return launch_persistent<k_slab<T, N, M, G, CL, S, X2>>(S * N, w.first[w.njobs] * (N / S), s, w);
+    constexpr bool PRE = MODE == SLAB_X2X1X1X2 ? Lc::slab_pre_b : Lc::slab_pre;
+    const long long units = w.first[w.njobs] * (N / S);
+    if constexpr (MODE == SLAB_X2X1X1X2 || MODE == SLAB_X2X1) {
+        if (partials)
+            return launch_persistent<k_slab<T, N, M, G, CL, S, MODE, PRE, true>>(S * N, units, s, w, partials);
+    }
+    return launch_persistent<k_slab<T, N, M, G, CL, S, MODE, PRE, false>>(S * N, units, s, w, nullptr);
 }
 
-template <typename T, int N, int M, int G, int CL, int AXIS>
+template <typename T, int N, int M, int G, int CL, int AXIS, int NSW>
 hipError_t launch_pencil(const Work& w, double* partials, hipStream_t s)
 {
     using Lc = Launch<T, N>;
     constexpr int NT = Lc::pencil_nt;
     const unsigned grid = (unsigned)(w.first[w.njobs] * (N * N / NT));
-    if (partials)
-        hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, AXIS, true>), dim3(grid), dim3(NT), 0, s, w, partials);
+    if (AXIS == 2 && partials)
+        hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, AXIS, NSW, AXIS == 2>), dim3(grid), dim3(NT), 0, s, w,
+                           partials);
     else
-        hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, AXIS, false>), dim3(grid), dim3(NT), 0, s, w, partials);
+        hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, AXIS, NSW, false>), dim3(grid), dim3(NT), 0, s, w, partials);
     return hipGetLastError();
 }
 
@@ -106,13 +119,15 @@ const KernelSet* kernel_set()
         G,
         CL,
         Lc::cube_fits ? &launch_cube<T, N, M, G, CL> : nullptr,
-        &launch_slab<T, N, M, G, CL, false>,
-        &launch_slab<T, N, M, G, CL, true>,
-        &launch_pencil<T, N, M, G, CL, 1>,
-        &launch_pencil<T, N, M, G, CL, 2>,
+        {&launch_slab<T, N, M, G, CL, SLAB_X1>, &launch_slab<T, N, M, G, CL, SLAB_X1X2>,
+         &launch_slab<T, N, M, G, CL, SLAB_X2X1X1X2>, &launch_slab<T, N, M, G, CL, SLAB_X2X1>},
+        &launch_pencil<T, N, M, G, CL, 1, 1>,
+        &launch_pencil<T, N, M, G, CL, 2, 1>,
+        &launch_pencil<T, N, M, G, CL, 2, 2>,
         &launch_reduce<T, N>,
         1,
         N * N / Lc::pencil_nt,
+        N / Lc::slab_s,
     };
     return &ks;
 }

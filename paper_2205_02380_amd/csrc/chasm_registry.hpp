@@ -19,22 +19,26 @@ struct KernelSet {
     int dtype;              // 0 float, 1 double
     int N, M, G, CL;
     LaunchFn cube;          // nullptr when the x-cube does not fit in LDS
-    LaunchFn slab_x1;
-    LaunchFn slab_x1x2;
+    // x3-slab passes by sweep sequence: [0] x1, [1] x1 x2, [2] x2 x1 x1 x2 (partials
+    // after the first x1), [3] x2 x1 (partials after x1)
+    LaunchFn slab[4];
     LaunchFn pencil_x2;
-    LaunchFn pencil_x3;
+    LaunchFn pencil_x3;     // partials after the x3 sweep
+    LaunchFn pencil_x3x3;   // two x3 sweeps, partials after the first
     LaunchFn reduce;        // diagnostics of the current field (one partial row per item)
     int cube_rows;          // partial rows per item written by cube (1)
-    int pencil_rows;        // partial rows per item written by pencil_x3
+    int pencil_rows;        // partial rows per item written by the x3 pencils
+    int slab_rows;          // partial rows per item written by the slab passes
 };
 
 template <typename T, int N, int M, int G, int CL>
 const KernelSet* kernel_set();
 
-// (T, N, M, G, CL) shapes, grouped by (N, dtype): one compilation unit per group.
+// (T, N, M, G, CL) shapes, grouped by (N, dtype); the build compiles each shape in a
+// generated unit of its own.
 // FP32: the benchmark and serving grids, the autotuner's patch x ghost sweep for the
-// 32^3 / 48^3 / 64^3 grids, and the test shapes.  FP64: the plain FP64 form and the
-// FP64 parity cases.
+// 32^3 / 48^3 / 64^3 grids, and the test shapes.  FP64: the plain FP64 form (also at
+// the 48^3 and 64^3 grids) and the FP64 parity cases.
 #define CHASM_SHAPES_N8_F32(X) X(float, 8, 2, 1, 0) X(float, 8, 4, 3, 0) X(float, 8, 8, 7, 0) X(float, 8, 4, 3, 2)
 #define CHASM_SHAPES_N8_F64(X) X(double, 8, 2, 1, 0) X(double, 8, 4, 3, 0) X(double, 8, 8, 7, 0) X(double, 8, 4, 3, 2)
 #define CHASM_SHAPES_N16_F32(X)                                                                        \
@@ -56,9 +60,11 @@ const KernelSet* kernel_set();
 #define CHASM_SHAPES_N64_F32(X)                                                                        \
     X(float, 64, 8, 4, 0) X(float, 64, 8, 6, 0) X(float, 64, 8, 8, 0) X(float, 64, 16, 4, 0)             \
     X(float, 64, 16, 6, 0) X(float, 64, 16, 8, 0)
+#define CHASM_SHAPES_N48_F64(X) X(double, 48, 16, 8, 0)
+#define CHASM_SHAPES_N64_F64(X) X(double, 64, 16, 8, 0)
 #define CHASM_SHAPES(X)                                                                                   \
     CHASM_SHAPES_N8_F32(X) CHASM_SHAPES_N8_F64(X) CHASM_SHAPES_N16_F32(X) CHASM_SHAPES_N16_F64(X)          \
     CHASM_SHAPES_N24_F32(X) CHASM_SHAPES_N24_F64(X) CHASM_SHAPES_N32_F32(X) CHASM_SHAPES_N32_F64(X)        \
-    CHASM_SHAPES_N48_F32(X) CHASM_SHAPES_N64_F32(X)
+    CHASM_SHAPES_N48_F32(X) CHASM_SHAPES_N48_F64(X) CHASM_SHAPES_N64_F32(X) CHASM_SHAPES_N64_F64(X)
 
 }  // namespace chasm

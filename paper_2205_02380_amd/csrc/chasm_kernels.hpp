@@ -107,8 +107,8 @@ __device__ __forceinline__ void vset<double>(double2& v, int i, double x)
 //    be in the memory-side cache; streamed accesses do not allocate there.  Measured
 //    on C2 (537 MB field): 0.194 ms per step streamed in either order, 0.181 ms with
 //    default caching and alternating order.
-//  - k_slab keeps plain vector accesses (streaming its strided scalar stores raised its
-//    write traffic by 4 %).
+//  - k_slab takes its policy as a template argument (see Launch::slab_cpol): streamed
+//    at N = 64, default caching at N = 48.
 // Results are bitwise equal under every policy.
 constexpr int kCpolStream = 2;
 constexpr int kCpolCube = 0;
@@ -426,7 +426,7 @@ enum SlabMode { SLAB_X1 = 0, SLAB_X1X2 = 1, SLAB_X2X1X1X2 = 2, SLAB_X2X1 = 3 };
 // writes.
 // RED: FP64 partials of the field after the sweep that completes a step (the first
 // x1 sweep of SLAB_X2X1X1X2, the x1 sweep of SLAB_X2X1), one row per unit.
-template <typename T, int N, int M, int G, int CL, int S, int MODE, bool PRE, bool RED>
+template <typename T, int N, int M, int G, int CL, int S, int MODE, bool PRE, bool RED, int CP = 0>
 __global__ __launch_bounds__(S * N) void k_slab(const Work w, double* __restrict__ partials)
 {
     constexpr int PX = N + 1;
@@ -443,12 +443,16 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w, double* __restrict
     long long u = blockIdx.x;
     if (u >= units) return;
     V pre[RV];
+    constexpr uint32_t UNIT_BYTES = (uint32_t)(S * N * N * sizeof(T));
     auto fetch = [&](long long uu) {
         long long it;
         const JobDev& jb = job_of(w, uu / BPI, it);
-        const V* src = reinterpret_cast<const V*>(static_cast<const T*>(jb.f) + it * (long long)(N * N * N) +
-                                                  (long long)(uu % BPI) * S * N * N);
-        static_for<0, RV>([&](auto qc) { pre[decltype(qc)::value] = src[decltype(qc)::value * NT + threadIdx.x]; });
+        const Buf b(static_cast<const T*>(jb.f) + it * (long long)(N * N * N) + (long long)(uu % BPI) * S * N * N,
+                    UNIT_BYTES);
+        static_for<0, RV>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            pre[q] = b.template load16<T, CP>(threadIdx.x * 16u, (uint32_t)(q * NT * 16));
+        });
     };
     if constexpr (PRE) fetch(u);
     for (;;) {
@@ -523,26 +527,29 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w, double* __restrict
         __syncthreads();
 
         if constexpr (MODE == SLAB_X1 || MODE == SLAB_X2X1) {
-            V* dst = reinterpret_cast<V*>(out_ptr);
-#pragma unroll
-            for (int e = threadIdx.x; e < S * N * N / VW; e += NT) {
+            const Buf ob(out_ptr, UNIT_BYTES);
+            static_for<0, RV>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                const int e = q * NT + threadIdx.x;
                 const int row = (e * VW) / N, x1 = (e * VW) % N;
                 V x;
 #pragma unroll
                 for (int i = 0; i < VW; ++i) vset<T>(x, i, lds[row * PX + x1 + i]);
-                dst[e] = x;
-            }
+                ob.template store16<T, CP>(x, threadIdx.x * 16u, (uint32_t)(q * NT * 16));
+            });
         } else {
             // x2 on the columns, stored straight to global memory
             int sigma;
             const auto kc = axis_coef<T>(job, 1, ik[1], sigma);
             const int base = slab_t * N * PX + col_t;
-            T* out = out_ptr + slab_t * N * N + col_t;
+            const Buf ob(out_ptr, UNIT_BYTES);
+            const uint32_t voff = (uint32_t)((slab_t * N * N + col_t) * sizeof(T));
             dispatch_sigma(sigma, [&](auto sc) {
                 T v[N];
 #pragma unroll
                 for (int i = 0; i < N; ++i) v[i] = lds[base + i * PX];
-                advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { out[j * N] = x; });
+                advect_line<T, N, M, G, CL, decltype(sc)::value>(
+                    v, kc, sigma, [&](int j, T x) { ob.template store<T, CP>(x, voff, (uint32_t)(j * N * sizeof(T))); });
             });
         }
         if constexpr (RED) {

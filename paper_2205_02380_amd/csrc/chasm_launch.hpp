@@ -22,11 +22,16 @@ struct Launch {
     // lines per pencil block: a multiple of 64 dividing N*N.
     static constexpr int pencil_nt = N == 8 ? 64 : (N == 24 ? 192 : 256);
     // Slab passes keep the next unit's loads in flight in VGPRs (see k_slab) where a
-    // line is at most 256 bytes; SLAB_X2X1X1X2 (four sweeps per unit) trades that for
-    // occupancy: at N = 64 in FP32 it needs 156 VGPRs without the prefetch (three
-    // waves per SIMD), 221 with it.
+    // line is at most 256 bytes.  For N = 64 (one 16 KB plane per 64-thread block, four
+    // sweeps in SLAB_X2X1X1X2) the occupancy is bound by LDS (nine planes per CU), so
+    // the prefetch costs nothing and hides the next plane's latency: 14.9 -> 13.7 ms per
+    // pass on the 64^3 x 32^3 grid, with streamed (nontemporal) field accesses
+    // (slab_cpol) a further 2 %.  For N = 48 (four planes per block) the four-sweep pass
+    // is faster without the prefetch (3 waves per SIMD instead of 2) and with default
+    // caching (2.55 ms against 2.65-2.85 ms for the other three forms).
     static constexpr bool slab_pre = sizeof(T) * N <= 256;
-    static constexpr bool slab_pre_b = false;
+    static constexpr bool slab_pre_b = sizeof(T) == 4 && N == 64;
+    static constexpr int slab_cpol = N == 64 ? kCpolStream : 0;
     static constexpr int reduce_nt = 256;
 };
 
@@ -77,12 +82,13 @@ hipError_t launch_slab(const Work& w, double* partials, hipStream_t s)
     using Lc = Launch<T, N>;
     constexpr int S = Lc::slab_s;
     constexpr bool PRE = MODE == SLAB_X2X1X1X2 ? Lc::slab_pre_b : Lc::slab_pre;
+    constexpr int CP = Lc::slab_cpol;
     const long long units = w.first[w.njobs] * (N / S);
     if constexpr (MODE == SLAB_X2X1X1X2 || MODE == SLAB_X2X1) {
         if (partials)
-            return launch_persistent<k_slab<T, N, M, G, CL, S, MODE, PRE, true>>(S * N, units, s, w, partials);
+            return launch_persistent<k_slab<T, N, M, G, CL, S, MODE, PRE, true, CP>>(S * N, units, s, w, partials);
     }
-    return launch_persistent<k_slab<T, N, M, G, CL, S, MODE, PRE, false>>(S * N, units, s, w, nullptr);
+    return launch_persistent<k_slab<T, N, M, G, CL, S, MODE, PRE, false, CP>>(S * N, units, s, w, nullptr);
 }
 
 template <typename T, int N, int M, int G, int CL, int AXIS, int NSW>

@@ -136,6 +136,22 @@ chasm_status chasm_advect_mass(chasm_advect_t h, double* mass, double* l2, doubl
  * Synchronises the handle's stream. */
 chasm_status chasm_advect_diagnostics(chasm_advect_t h, double* out);
 
+/* Allocation-free form of chasm_advect_diagnostics, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  No handle: desc describes the field f_dev (same rules as
+ * chasm_advect_create; the FP64 results are those chasm_advect_diagnostics returns for
+ * a handle over f_dev, bitwise).  out_dev: caller-owned DEVICE memory of nbatch*8
+ * doubles, written as out_dev[b*8 + i] (i = mass, l2, x1, x2, x3, k1, k2, k3, all times
+ * V).  Asynchronous on hip_stream; nothing is allocated and nothing is copied to the
+ * host.  The partial sums live in a fixed 16 MiB device workspace of the library (one
+ * per GPU, held until the process ends): fields whose nbatch*prod(nk) partial rows
+ * (64 bytes each, plus 16 KiB per batch member) exceed it return CHASM_EINVAL.  Every
+ * call on a GPU shares that GPU's workspace, so calls that overlap on one GPU (other
+ * streams or threads) race; serialise them.
+ * Errors: EINVAL (bad descriptor, pointer or size), EUNSUPPORTED, EDEVICE. */
+chasm_status chasm_advect_diagnostics_noalloc(const chasm_advect_desc* desc, const void* f_dev, void* hip_stream,
+                                              double* out_dev);
+
 /* The visualisation observables of Sec. 5 for each batch member b, in FP64 (host
  * arrays; any may be NULL to skip it):
  *   w1[b][k1][x1] = W_1(x1, k1) = integral of f over x2, x3, k2, k3  (nbatch*nk[0]*nx[0])

@@ -63,6 +63,7 @@ EXPORTS = (
     "chasm_advect_create", "chasm_advect_step", "chasm_advect_mass", "chasm_advect_diagnostics",
     "chasm_advect_history", "chasm_advect_step_many", "chasm_advect_workspace_bytes", "chasm_advect_schedule",
     "chasm_advect_destroy", "chasm_advect_last_error", "chasm_advect_version", "chasm_advect_marginals",
+    "chasm_advect_diagnostics_noalloc",
 )
 
 _lib = None
@@ -88,10 +89,11 @@ def lib():
     L.chasm_advect_schedule.argtypes = [vp, ctypes.POINTER(i32)]
     L.chasm_advect_destroy.argtypes = [vp]
     L.chasm_advect_marginals.argtypes = [vp, pd, pd, pd, pd]
+    L.chasm_advect_diagnostics_noalloc.argtypes = [pdesc, vp, vp, vp]
     L.chasm_advect_last_error.restype = ctypes.c_char_p
     L.chasm_advect_version.restype = ctypes.c_char_p
     for name in ("create", "step", "mass", "diagnostics", "history", "step_many", "workspace_bytes", "schedule",
-                 "destroy", "marginals"):
+                 "destroy", "marginals", "diagnostics_noalloc"):
         getattr(L, "chasm_advect_" + name).restype = ctypes.c_int
     _lib = L
     return L
@@ -147,6 +149,13 @@ def chasm_advect_diagnostics(h: int, nbatch: int) -> np.ndarray:
     out = np.zeros((nbatch, NRED))
     _check(lib().chasm_advect_diagnostics(ctypes.c_void_p(h), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out
+
+
+def chasm_advect_diagnostics_noalloc(desc: chasm_advect_desc, f_dev: int, hip_stream: int, out_dev: int) -> None:
+    """Allocation-free diagnostics of the field at f_dev into the device buffer out_dev
+    (nbatch*8 doubles); asynchronous on hip_stream."""
+    _check(lib().chasm_advect_diagnostics_noalloc(ctypes.byref(desc), ctypes.c_void_p(f_dev),
+                                                  ctypes.c_void_p(hip_stream), ctypes.c_void_p(out_dev)))
 
 
 def chasm_advect_history(h: int, nbatch: int, max_steps: int) -> np.ndarray:

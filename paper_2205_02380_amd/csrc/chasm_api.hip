@@ -113,6 +113,37 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
     if (hist && threadIdx.x == 0) *counter = *counter + 1;
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device workspace of chasm_advect_diagnostics_noalloc: per-item partial rows,
+// fold rows and the finalized results of one call.  Each device holds its own copy
+// for the life of the process.  Host code never passes `scratch` itself to a kernel
+// (in host code the name is only a stand-in for the device array): it takes the
+// array's device address, per device, from hipGetSymbolAddress and uses that.
+constexpr size_t kNoAllocBytes = 16u << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static void* g_scratch_dev[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device (looked up once per device).
+static hipError_t noalloc_scratch(void** ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = p;
+    }
+    *ptr = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
 }  // namespace chasm
 
 using namespace chasm;
@@ -793,6 +824,66 @@ chasm_status chasm_advect_diagnostics(chasm_advect_t h, double* out)
     if (e != hipSuccess) return hip_fail(h, e, "diagnostics copy");
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+    return CHASM_OK;
+}
+
+chasm_status chasm_advect_diagnostics_noalloc(const chasm_advect_desc* desc, const void* f_dev, void* hip_stream,
+                                              double* out_dev)
+{
+    const KernelSet* ks = nullptr;
+    chasm_status st = validate(desc, &ks);
+    if (st != CHASM_OK) return st;
+    if (!f_dev || !out_dev) return fail(CHASM_EINVAL, "f_dev and out_dev must be device pointers");
+    if (((uintptr_t)f_dev) % 16) return fail(CHASM_EINVAL, "f_dev must be 16-byte aligned");
+    const long long nkp = (long long)desc->nk[0] * desc->nk[1] * desc->nk[2];
+    const long long items = nkp * desc->nbatch;
+    // workspace: one FP64 partial row per item, the fold rows, the results
+    const size_t part_b = ((size_t)items * NRED * sizeof(double) + 255) & ~(size_t)255;
+    const size_t fold_b = ((size_t)desc->nbatch * FOLD_CHUNKS * NRED * sizeof(double) + 255) & ~(size_t)255;
+    if (part_b + fold_b > kNoAllocBytes) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "%lld items need %zu bytes of partials, more than the %zu-byte no-allocation workspace",
+                      items, part_b + fold_b, kNoAllocBytes);
+        return fail(CHASM_EINVAL, buf);
+    }
+    void* ws = nullptr;
+    hipError_t e = noalloc_scratch(&ws);
+    if (e != hipSuccess) return fail(CHASM_EDEVICE, std::string("workspace lookup: ") + hipGetErrorString(e));
+    double* part = static_cast<double*>(ws);
+    double* fold = reinterpret_cast<double*>(static_cast<char*>(ws) + part_b);
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    Work w{};
+    w.njobs = 1;
+    w.first[0] = 0;
+    w.first[1] = items;
+    w.jobs[0].f = const_cast<void*>(f_dev);
+    w.jobs[0].out = const_cast<void*>(f_dev);
+    w.jobs[0].nitems = items;
+    FinalizeArgs fin{};
+    for (int a = 0; a < 3; ++a) {
+        w.jobs[0].nk[a] = desc->nk[a];
+        fin.xlo[a] = desc->x_lo[a];
+        fin.hx[a] = (desc->x_hi[a] - desc->x_lo[a]) / desc->nx[a];
+        fin.klo[a] = desc->k_lo[a];
+        fin.hk[a] = (desc->k_hi[a] - desc->k_lo[a]) / desc->nk[a];
+    }
+    fin.vol = fin.hx[0] * fin.hx[1] * fin.hx[2] * fin.hk[0] * fin.hk[1] * fin.hk[2];
+    // the same kernels and summation order as chasm_advect_diagnostics
+    e = ks->reduce(w, part, s);
+    if (e != hipSuccess) return fail(CHASM_EDEVICE, std::string("reduce launch: ") + hipGetErrorString(e));
+    const double* src = part;
+    long long rows = nkp;
+    if (rows > FOLD_MIN_ROWS) {
+        hipLaunchKernelGGL(k_fold, dim3(FOLD_CHUNKS, desc->nbatch), dim3(256), 0, s, part, rows, fold);
+        src = fold;
+        rows = FOLD_CHUNKS;
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, src, rows, fin, out_dev, nullptr, nullptr, 1,
+                       desc->nbatch);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(CHASM_EDEVICE, std::string("finalize launch: ") + hipGetErrorString(e));
     return CHASM_OK;
 }
 

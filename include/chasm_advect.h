@@ -50,7 +50,8 @@ typedef enum {
     CHASM_ENOMEM = -2,        /* device or host allocation failed */
     CHASM_EDEVICE = -3,       /* a HIP call or kernel launch failed */
     CHASM_ESTATE = -4,        /* handle poisoned by an earlier device failure */
-    CHASM_EUNSUPPORTED = -5   /* valid, but no kernel is built for this shape */
+    CHASM_EUNSUPPORTED = -5   /* valid, but beyond a resource limit of the kernels (or a
+                                 schedule the shape's kernels do not provide) */
 } chasm_status;
 
 typedef enum { CHASM_F32 = 0, CHASM_F64 = 1 } chasm_dtype;
@@ -69,11 +70,20 @@ typedef enum {
      * rows of the inverse of the global matrix with the Hermite boundary rows of
      * eq. 2.13 and zero end slopes, truncated to |j - I| <= ghost; the slopes at both
      * line ends are 0. */
-    CHASM_CLOSURE_NEUMANN = 2
+    CHASM_CLOSURE_NEUMANN = 2,
+    /* The paper's PMBC with the Hermite global condition of eq. 2.13 and given end
+     * slopes: s'(x_lo) = slope_lo[d], s'(x_last) = slope_hi[d] on every line along axis
+     * d (the Neumann closure is the case of zero slopes).  Interface slopes come from
+     * the rows of the inverse of that global matrix: the data columns truncated to
+     * |j - I| <= ghost, and the columns of the two given slopes kept for interfaces
+     * within ghost of their end (reading in the design notes).  Runs on the
+     * runtime-shape kernels. */
+    CHASM_CLOSURE_HERMITE = 3
 } chasm_closure;
 
 typedef enum {
-    CHASM_SCHED_AUTO = 0,     /* CUBE when the x-cube fits in LDS, else SLAB */
+    CHASM_SCHED_AUTO = 0,     /* CUBE when the x-cube fits in LDS, else SLAB; PLAIN on the
+                                 runtime-shape kernels */
     CHASM_SCHED_CUBE = 1,     /* one launch per step, all three sweeps in LDS */
     CHASM_SCHED_SLAB = 2,     /* two launches per step: x1+x2 on x3-slabs, then x3 */
     CHASM_SCHED_PLAIN = 3     /* three launches per step, one per axis */
@@ -91,15 +101,21 @@ enum {
      * The arithmetic is unchanged (results are bitwise equal to in place); HBM serves a
      * read stream and a write stream to different addresses faster than read-modify-
      * write traffic on one buffer.  chasm_advect_step_many steps CUBE handles in place. */
-    CHASM_FLAG_OUT_OF_PLACE = 1u << 2
+    CHASM_FLAG_OUT_OF_PLACE = 1u << 2,
+    /* Use the runtime-shape kernels even where compiled kernels exist for the shape
+     * (every descriptor the compiled kernels do not cover uses them anyway): one launch
+     * per axis sweep with the tables read from device memory, the PLAIN schedule. */
+    CHASM_FLAG_RUNTIME_SHAPE = 1u << 3
 };
 
 typedef struct {
-    int32_t nx[3];            /* x nodes per axis; the kernels need nx[0]==nx[1]==nx[2] */
+    int32_t nx[3];            /* x nodes per axis (>= 2); grids with equal nx and patch on the
+                                 three axes and a compiled (nx, patch, ghost) run the compiled
+                                 kernels, every other grid the runtime-shape kernels */
     int32_t nk[3];            /* k nodes per axis (>= 1) */
     double x_lo[3], x_hi[3];  /* half-open x extents */
     double k_lo[3], k_hi[3];  /* half-open k extents */
-    int32_t patch[3];         /* cells per patch M_d (>= 1); the kernels need equal M_d */
+    int32_t patch[3];         /* cells per patch M_d (>= 1) */
     int32_t ghost;            /* PMBC stencil half-width g = n_nb (>= 1; >= 3 for POLY3) */
     double dt;                /* time step (hbar = m = 1) */
     int32_t dtype;            /* chasm_dtype */
@@ -108,6 +124,7 @@ typedef struct {
     uint32_t flags;           /* CHASM_FLAG_* */
     int32_t schedule;         /* chasm_schedule */
     int32_t history_cap;      /* steps of diagnostics kept with REDUCE_EACH_STEP (0: 1024) */
+    double slope_lo[3], slope_hi[3];   /* end slopes of CHASM_CLOSURE_HERMITE (else ignored) */
 } chasm_advect_desc;
 
 /* Create a handle that advances the caller's field f_dev in place.
@@ -116,8 +133,9 @@ typedef struct {
  * f_dev: device pointer, 16-byte aligned, nbatch*prod(nk)*prod(nx) elements of the
  *   dtype; owned by the caller, never freed by the library, must outlive the handle.
  * hip_stream: stream all work of this handle is issued on.
- * Errors: EINVAL (bad descriptor or pointer), EUNSUPPORTED (no kernel for this
- *   shape), ENOMEM, EDEVICE. */
+ * Errors: EINVAL (bad descriptor or pointer), EUNSUPPORTED (beyond a resource limit:
+ *   a line too long for the LDS tiles, a launch grid beyond 2^31 blocks; or CUBE/SLAB
+ *   asked of the runtime-shape kernels), ENOMEM, EDEVICE. */
 chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, void* hip_stream,
                                  chasm_advect_t* out);
 

@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "libchasm_oracle.so")
 PMBC = 0    # paper closure: truncated rows of the natural-BC inverse (eqs. 3.4-3.5)
 POLY3 = 1   # cubic-exact variant of those rows (not in the paper; see module docstring of the C file)
 NEUMANN = 2  # rows of the inverse of the zero-slope Hermite (Neumann) global matrix (eq. 2.13)
+HERMITE = 3  # the Hermite global matrix (eq. 2.13) with given end slopes phi_L, phi_R
 
 _lib = None
 
@@ -56,6 +57,10 @@ def _load():
     lib.chasm_oracle_global_line_bc.argtypes = [i, d, i, d, pd, pd]
     lib.chasm_oracle_global_inverse.argtypes = [i, d, i, pd]
     lib.chasm_oracle_advect6d.argtypes = [pi, pd, pi, pd, pd, pi, i, i, d, i, i, pi, pd, i]
+    lib.chasm_oracle_advect6d_bc.argtypes = [pi, pd, pi, pd, pd, pi, i, i, pd, pd, d, i, i, pi, pd, i]
+    lib.chasm_oracle_stencils_bc.argtypes = [i, i, i, d, i, d, d, pd, pd]
+    lib.chasm_oracle_line_bc.argtypes = [i, i, d, i, pd, pd, d, pd, pd]
+    lib.chasm_oracle_global_line_hermite.argtypes = [i, d, d, d, d, pd, pd]
     lib.chasm_oracle_reduce.argtypes = [pi, pd, pd, pi, pd, pd, i, pd, pd]
     _lib = lib
     return lib
@@ -101,6 +106,37 @@ def stencils(N: int, M: int, g: int, h: float, closure: int = PMBC) -> np.ndarra
     p = npatch(N, M)
     out = np.zeros((p + 1, N))
     _check(_load().chasm_oracle_stencils(N, M, g, float(h), closure, _dp(out)), "stencils")
+    return out
+
+
+def stencils_bc(N: int, M: int, g: int, h: float, closure: int = PMBC, slopes=(0.0, 0.0)):
+    """Interface rows and, for closure HERMITE, the end-slope part of each interface
+    slope (eq. 2.13 columns of the global inverse, truncated): (c, bias)."""
+    p = npatch(N, M)
+    c = np.zeros((p + 1, N))
+    bias = np.zeros(p + 1)
+    _check(_load().chasm_oracle_stencils_bc(N, M, g, float(h), closure, float(slopes[0]), float(slopes[1]), _dp(c),
+                                            _dp(bias)), "stencils_bc")
+    return c, bias
+
+
+def line_bc(N: int, M: int, g: int, h: float, alpha: float, phi, closure: int = HERMITE,
+            slopes=(0.0, 0.0)) -> np.ndarray:
+    """One patched sweep of one line with the end slopes of closure HERMITE."""
+    c, bias = stencils_bc(N, M, g, h, closure, slopes)
+    phi = _f64(phi)
+    out = np.zeros(N)
+    _check(_load().chasm_oracle_line_bc(N, M, float(h), closure, _dp(c), _dp(bias), float(alpha), _dp(phi),
+                                        _dp(out)), "line_bc")
+    return out
+
+
+def global_line_hermite(N: int, h: float, alpha: float, phi, slopes=(0.0, 0.0)) -> np.ndarray:
+    """Brute-force global spline with the Hermite rows of eq. 2.13 and given end slopes."""
+    phi = _f64(phi)
+    out = np.zeros(N)
+    _check(_load().chasm_oracle_global_line_hermite(N, float(h), float(slopes[0]), float(slopes[1]), float(alpha),
+                                                    _dp(phi), _dp(out)), "global_line_hermite")
     return out
 
 
@@ -155,11 +191,12 @@ def global_inverse(N: int, h: float, bc: int) -> np.ndarray:
 
 
 def advect6d(cubes: np.ndarray, nx, hx, nk, klo, hk, M, g: int, dt: float, nsteps: int,
-             closure: int = PMBC, kidx=None, nthreads: int = 0) -> np.ndarray:
+             closure: int = PMBC, kidx=None, nthreads: int = 0, slopes=None) -> np.ndarray:
     """nsteps of the 6-D step (Sec. 3.2): x1, x2, x3 sweeps per k-point.
 
     cubes: full field [k3][k2][k1][x3][x2][x1] (kidx None) or an array of cubes
-    [n][x3][x2][x1] whose k-points are kidx[n] = (i1, i2, i3).  Returns a new array."""
+    [n][x3][x2][x1] whose k-points are kidx[n] = (i1, i2, i3).  slopes: per axis
+    (slope_lo, slope_hi) of closure HERMITE.  Returns a new array."""
     f = np.array(cubes, dtype=np.float64, copy=True, order="C")
     nx_a = np.ascontiguousarray(nx, dtype=np.int32)
     nk_a = np.ascontiguousarray(nk, dtype=np.int32)
@@ -176,9 +213,11 @@ def advect6d(cubes: np.ndarray, nx, hx, nk, klo, hk, M, g: int, dt: float, nstep
         kp = np.ascontiguousarray(kidx, dtype=np.int32).reshape(-1, 3)
         if kp.shape[0] != nkp:
             raise ValueError("kidx length does not match the number of cubes")
-    rc = _load().chasm_oracle_advect6d(
+    sl = np.zeros((3, 2)) if slopes is None else np.asarray(slopes, dtype=np.float64).reshape(3, 2)
+    lo, hi = np.ascontiguousarray(sl[:, 0]), np.ascontiguousarray(sl[:, 1])
+    rc = _load().chasm_oracle_advect6d_bc(
         _ip(nx_a), _dp(_f64(hx)), _ip(nk_a), _dp(_f64(klo)), _dp(_f64(hk)), _ip(M_a), int(g), int(closure),
-        float(dt), int(nsteps), int(nkp), None if kp is None else _ip(kp), _dp(f), int(nthreads))
+        _dp(lo), _dp(hi), float(dt), int(nsteps), int(nkp), None if kp is None else _ip(kp), _dp(f), int(nthreads))
     _check(rc, "advect6d")
     return f
 

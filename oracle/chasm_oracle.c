@@ -34,6 +34,12 @@
  *   - optional closure NEUMANN: the global matrix takes the Hermite boundary rows of
  *     eq. 2.13 with zero end slopes (the Neumann condition the paper names as the
  *     alternative to the natural one); stencils are rows of its inverse;
+ *   - optional closure HERMITE: the same matrix with given end slopes phi_L, phi_R
+ *     (eq. 2.13) on the right-hand side of its boundary rows.  The interface slope
+ *     then has a data part (truncated to |j - I| <= g as above) and the parts
+ *     c_L(I) phi_L + c_R(I) phi_R from the inverse's columns of the boundary rows;
+ *     those two columns belong to the virtual nodes -1 and N one cell beyond the
+ *     ends and are kept under the same distance rule: |(-1) - I| <= g, |N - I| <= g;
  *   - optional closure POLY3 (not in the paper): the truncated stencil rows get the
  *     minimum-norm correction that makes them exact for cubic data, and the outer
  *     ghost coefficient is extrapolated by a zero fourth difference, so cubic
@@ -49,6 +55,7 @@
 #define ORACLE_CLOSURE_PMBC 0
 #define ORACLE_CLOSURE_POLY3 1
 #define ORACLE_CLOSURE_NEUMANN 2
+#define ORACLE_CLOSURE_HERMITE 3
 
 /* ------------------------------------------------------------------------- */
 /* Cubic B-spline centred at 0, support [-2, 2]: eq. (2.10) with x = x_nu + t*h. */
@@ -201,21 +208,43 @@ int chasm_oracle_global_inverse(int N, double h, int bc, double *inv)
  * N (zeros outside the band), row q for interface I_q.
  * closure POLY3 adds the minimum-2-norm correction so that each row differentiates
  * cubic data exactly. */
+int chasm_oracle_stencils_bc(int N, int M, int g, double h, int closure, double phi_l, double phi_r,
+                             double *c, double *bias);
+
 int chasm_oracle_stencils(int N, int M, int g, double h, int closure, double *c)
+{
+    if (closure == ORACLE_CLOSURE_HERMITE) return -1;
+    return chasm_oracle_stencils_bc(N, M, g, h, closure, 0.0, 0.0, c, NULL);
+}
+
+/* The rows above and, for closure HERMITE, bias[q] = c_L(I_q) phi_L + c_R(I_q) phi_R
+ * (truncated; bias may be NULL for the other closures, else it is set to 0). */
+int chasm_oracle_stencils_bc(int N, int M, int g, double h, int closure, double phi_l, double phi_r,
+                             double *c, double *bias)
 {
     int p = chasm_oracle_npatch(N, M);
     if (p < 1 || g < 1 || !(h > 0.0)) return -1;
-    if (closure != ORACLE_CLOSURE_PMBC && closure != ORACLE_CLOSURE_POLY3 && closure != ORACLE_CLOSURE_NEUMANN)
+    if (closure != ORACLE_CLOSURE_PMBC && closure != ORACLE_CLOSURE_POLY3 && closure != ORACLE_CLOSURE_NEUMANN &&
+        closure != ORACLE_CLOSURE_HERMITE)
         return -1;
+    if (closure == ORACLE_CLOSURE_HERMITE && !bias) return -1;
     int n = N + 2;
     double *inv = (double *)malloc((size_t)n * n * sizeof(double));
     if (!inv) return -2;
-    int rc = chasm_oracle_global_inverse(N, h, closure == ORACLE_CLOSURE_NEUMANN ? 1 : 0, inv);
+    int hermite_rows = closure == ORACLE_CLOSURE_NEUMANN || closure == ORACLE_CLOSURE_HERMITE;
+    int rc = chasm_oracle_global_inverse(N, h, hermite_rows ? 1 : 0, inv);
     if (rc) { free(inv); return rc; }
     memset(c, 0, (size_t)(p + 1) * N * sizeof(double));
+    if (bias) memset(bias, 0, (size_t)(p + 1) * sizeof(double));
     for (int q = 0; q <= p; ++q) {
         int I = (q < p) ? q * M : N - 1;
         double *row = c + (size_t)q * N;
+        if (closure == ORACLE_CLOSURE_HERMITE) {
+            /* boundary-row columns: phi_L is the right-hand side of row 0, phi_R of row N+1 */
+            if (abs(-1 - I) <= g) bias[q] += (inv[(size_t)(I + 2) * n + 0] - inv[(size_t)I * n + 0]) / (2.0 * h) * phi_l;
+            if (abs(N - I) <= g)
+                bias[q] += (inv[(size_t)(I + 2) * n + (N + 1)] - inv[(size_t)I * n + (N + 1)]) / (2.0 * h) * phi_r;
+        }
         for (int j = 0; j < N; ++j) {
             if (abs(j - I) > g) continue;
             /* eta_{I+1} at position I+2, eta_{I-1} at position I; data phi_j is column j+1 */
@@ -255,14 +284,14 @@ int chasm_oracle_stencils(int N, int M, int g, double h, int closure, double *c)
  * (eq. 2.13) at both patch ends with slopes d_{I_l}, d_{I_{l+1}}, and interpolation
  * (eq. 2.12) at the m+1 patch nodes.  Result: eta[l * (M+5) + (nu+2)] for
  * nu = -2..m_l+2, where nu = -2 and nu = m_l+2 are the ghost coefficients. */
-static int patch_coefficients(int N, int M, double h, int closure, const double *c,
+static int patch_coefficients(int N, int M, double h, int closure, const double *c, const double *bias,
                               const double *phi, double *d, double *eta, double *work)
 {
     int p = chasm_oracle_npatch(N, M);
     for (int q = 0; q <= p; ++q) {
         double s = 0.0;
         for (int j = 0; j < N; ++j) s += c[(size_t)q * N + j] * phi[j];
-        d[q] = s;
+        d[q] = s + (bias ? bias[q] : 0.0);
     }
     int stride = M + 5;
     for (int l = 0; l < p; ++l) {
@@ -343,8 +372,37 @@ int chasm_oracle_line_coefficients(int N, int M, double h, int closure, const do
     double *d = (double *)malloc((size_t)(p + 1) * sizeof(double));
     double *work = (double *)malloc((size_t)(n * n + n) * sizeof(double));
     if (!d || !work) { free(d); free(work); return -2; }
-    int rc = patch_coefficients(N, M, h, closure, c, phi, d, eta, work);
+    int rc = patch_coefficients(N, M, h, closure, c, NULL, phi, d, eta, work);
     free(d); free(work);
+    return rc;
+}
+
+/* The same with the end-slope part of closure HERMITE (bias from chasm_oracle_stencils_bc). */
+int chasm_oracle_line_coefficients_bc(int N, int M, double h, int closure, const double *c, const double *bias,
+                                      const double *phi, double *eta)
+{
+    int p = chasm_oracle_npatch(N, M);
+    if (p < 1) return -1;
+    int n = M + 3;
+    double *d = (double *)malloc((size_t)(p + 1) * sizeof(double));
+    double *work = (double *)malloc((size_t)(n * n + n) * sizeof(double));
+    if (!d || !work) { free(d); free(work); return -2; }
+    int rc = patch_coefficients(N, M, h, closure, c, bias, phi, d, eta, work);
+    free(d); free(work);
+    return rc;
+}
+
+/* One sweep of one line under closure HERMITE (or any closure, bias NULL). */
+int chasm_oracle_line_bc(int N, int M, double h, int closure, const double *c, const double *bias, double alpha,
+                         const double *phi, double *out)
+{
+    int p = chasm_oracle_npatch(N, M);
+    if (p < 1) return -1;
+    double *eta = (double *)malloc((size_t)p * (M + 5) * sizeof(double));
+    if (!eta) return -2;
+    int rc = chasm_oracle_line_coefficients_bc(N, M, h, closure, c, bias, phi, eta);
+    if (!rc) patch_evaluate(N, M, alpha, eta, out);
+    free(eta);
     return rc;
 }
 
@@ -395,6 +453,31 @@ int chasm_oracle_global_line_bc(int N, double h, int bc, double alpha, const dou
     return 0;
 }
 
+/* Brute-force global reference of the Hermite condition with given end slopes:
+ * eta = A^{-1} (phi_L, phi_0..phi_{N-1}, phi_R), no patches, ghosts 0. */
+int chasm_oracle_global_line_hermite(int N, double h, double phi_l, double phi_r, double alpha, const double *phi,
+                                     double *out)
+{
+    int n = N + 2;
+    double *inv = (double *)malloc((size_t)n * n * sizeof(double));
+    double *eta = (double *)malloc((size_t)n * sizeof(double));
+    if (!inv || !eta) { free(inv); free(eta); return -2; }
+    int rc = chasm_oracle_global_inverse(N, h, 1, inv);
+    if (rc) { free(inv); free(eta); return rc; }
+    for (int u = 0; u < n; ++u) {
+        double s = inv[(size_t)u * n + 0] * phi_l + inv[(size_t)u * n + (N + 1)] * phi_r;
+        for (int j = 0; j < N; ++j) s += inv[(size_t)u * n + (j + 1)] * phi[j];
+        eta[u] = s;
+    }
+    for (int j = 0; j < N; ++j) {
+        double t = (double)j - alpha, acc = 0.0;
+        for (int nu = -1; nu <= N; ++nu) acc += eta[nu + 1] * chasm_oracle_bspline(t - (double)nu);
+        out[j] = acc;
+    }
+    free(inv); free(eta);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* 6-D step (Sec. 3.2): for each k-point independently, sweep x1 with
  * alpha_1 = k1*dt/h1, then x2, then x3, nsteps times.
@@ -402,24 +485,41 @@ int chasm_oracle_global_line_bc(int N, double h, int bc, double alpha, const dou
  * cubes are all k-points in [k3][k2][k1] order (nkp = nk1*nk2*nk3); otherwise
  * kidx[3*i..3*i+2] = (i1, i2, i3) gives the k-point of cube i.
  * g: stencil half-width; M[d]: patch cells per axis.  nthreads <= 0: default. */
+int chasm_oracle_advect6d_bc(const int nx[3], const double hx[3], const int nk[3],
+                             const double klo[3], const double hk[3], const int M[3], int g,
+                             int closure, const double slope_lo[3], const double slope_hi[3], double dt,
+                             int nsteps, int nkp, const int *kidx, double *cubes, int nthreads);
+
 int chasm_oracle_advect6d(const int nx[3], const double hx[3], const int nk[3],
                           const double klo[3], const double hk[3], const int M[3], int g,
                           int closure, double dt, int nsteps, int nkp, const int *kidx,
                           double *cubes, int nthreads)
 {
+    const double zero[3] = {0.0, 0.0, 0.0};
+    return chasm_oracle_advect6d_bc(nx, hx, nk, klo, hk, M, g, closure, zero, zero, dt, nsteps, nkp, kidx, cubes,
+                                    nthreads);
+}
+
+/* The same with the end slopes of closure HERMITE per axis (ignored otherwise). */
+int chasm_oracle_advect6d_bc(const int nx[3], const double hx[3], const int nk[3],
+                             const double klo[3], const double hk[3], const int M[3], int g,
+                             int closure, const double slope_lo[3], const double slope_hi[3], double dt,
+                             int nsteps, int nkp, const int *kidx, double *cubes, int nthreads)
+{
     if (nsteps < 0 || nkp < 0) return -1;
     if (!kidx && nkp != nk[0] * nk[1] * nk[2]) return -1;
-    double *c[3] = {0, 0, 0};
+    double *c[3] = {0, 0, 0}, *bias[3] = {0, 0, 0};
     int rc = 0;
     for (int d = 0; d < 3; ++d) {
         int p = chasm_oracle_npatch(nx[d], M[d]);
         if (p < 1) { rc = -1; break; }
         c[d] = (double *)malloc((size_t)(p + 1) * nx[d] * sizeof(double));
-        if (!c[d]) { rc = -2; break; }
-        rc = chasm_oracle_stencils(nx[d], M[d], g, hx[d], closure, c[d]);
+        bias[d] = (double *)malloc((size_t)(p + 1) * sizeof(double));
+        if (!c[d] || !bias[d]) { rc = -2; break; }
+        rc = chasm_oracle_stencils_bc(nx[d], M[d], g, hx[d], closure, slope_lo[d], slope_hi[d], c[d], bias[d]);
         if (rc) break;
     }
-    if (rc) { for (int d = 0; d < 3; ++d) free(c[d]); return rc; }
+    if (rc) { for (int d = 0; d < 3; ++d) { free(c[d]); free(bias[d]); } return rc; }
     size_t cube = (size_t)nx[0] * nx[1] * nx[2];
     int nmax = nx[0] > nx[1] ? nx[0] : nx[1];
     if (nx[2] > nmax) nmax = nx[2];
@@ -459,7 +559,7 @@ int chasm_oracle_advect6d(const int nx[3], const double hx[3], const int nk[3],
                         for (int a = 0; a < nx[oa]; ++a) {
                             size_t base = (size_t)a * sa + (size_t)b * sb;
                             for (int i = 0; i < nx[d]; ++i) phi[i] = f[base + (size_t)i * stride];
-                            if (patch_coefficients(nx[d], M[d], hx[d], closure, c[d], phi, dd, eta, work)) {
+                            if (patch_coefficients(nx[d], M[d], hx[d], closure, c[d], bias[d], phi, dd, eta, work)) {
                                 err = 1;
                                 break;
                             }
@@ -472,7 +572,7 @@ int chasm_oracle_advect6d(const int nx[3], const double hx[3], const int nk[3],
         }
         free(tmp); free(phi); free(out); free(eta); free(dd); free(work);
     }
-    for (int d = 0; d < 3; ++d) free(c[d]);
+    for (int d = 0; d < 3; ++d) { free(c[d]); free(bias[d]); }
     return err ? -3 : 0;
 }
 

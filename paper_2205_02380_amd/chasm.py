@@ -22,13 +22,13 @@ LIB_PATH = os.path.join(_HERE, "libchasm.so")
 
 CHASM_OK, CHASM_EINVAL, CHASM_ENOMEM, CHASM_EDEVICE, CHASM_ESTATE, CHASM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CHASM_F32, CHASM_F64 = 0, 1
-CHASM_CLOSURE_PMBC, CHASM_CLOSURE_POLY3, CHASM_CLOSURE_NEUMANN = 0, 1, 2
+CHASM_CLOSURE_PMBC, CHASM_CLOSURE_POLY3, CHASM_CLOSURE_NEUMANN, CHASM_CLOSURE_HERMITE = 0, 1, 2, 3
 CHASM_SCHED_AUTO, CHASM_SCHED_CUBE, CHASM_SCHED_SLAB, CHASM_SCHED_PLAIN = 0, 1, 2, 3
-CHASM_FLAG_REDUCE_EACH_STEP, CHASM_FLAG_GRAPH, CHASM_FLAG_OUT_OF_PLACE = 1, 2, 4
+CHASM_FLAG_REDUCE_EACH_STEP, CHASM_FLAG_GRAPH, CHASM_FLAG_OUT_OF_PLACE, CHASM_FLAG_RUNTIME_SHAPE = 1, 2, 4, 8
 
 SCHEDULES = {"auto": 0, "cube": 1, "slab": 2, "plain": 3}
 SCHEDULE_NAMES = {v: k for k, v in SCHEDULES.items()}
-CLOSURES = {"pmbc": 0, "poly3": 1, "neumann": 2}
+CLOSURES = {"pmbc": 0, "poly3": 1, "neumann": 2, "hermite": 3}
 NRED = 8
 DIAG_NAMES = ("mass", "l2", "x1", "x2", "x3", "k1", "k2", "k3")
 
@@ -56,6 +56,8 @@ class chasm_advect_desc(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("schedule", ctypes.c_int32),
         ("history_cap", ctypes.c_int32),
+        ("slope_lo", ctypes.c_double * 3),
+        ("slope_hi", ctypes.c_double * 3),
     ]
 
 
@@ -105,7 +107,9 @@ def _check(st: int) -> None:
 
 
 def make_desc(grid: Grid, patch, ghost: int, dt: float, dtype: str = "f32", closure: str = "pmbc",
-              nbatch: int = 1, flags: int = 0, schedule: str = "auto", history_cap: int = 0) -> chasm_advect_desc:
+              nbatch: int = 1, flags: int = 0, schedule: str = "auto", history_cap: int = 0,
+              slopes=None) -> chasm_advect_desc:
+    """slopes: ((lo1, hi1), (lo2, hi2), (lo3, hi3)) end slopes of the Hermite closure."""
     if isinstance(patch, int):
         patch = (patch, patch, patch)
     d = chasm_advect_desc()
@@ -123,6 +127,9 @@ def make_desc(grid: Grid, patch, ghost: int, dt: float, dtype: str = "f32", clos
     d.flags = int(flags)
     d.schedule = SCHEDULES[schedule]
     d.history_cap = int(history_cap)
+    if slopes is not None:
+        for a in range(3):
+            d.slope_lo[a], d.slope_hi[a] = float(slopes[a][0]), float(slopes[a][1])
     return d
 
 
@@ -214,7 +221,8 @@ class Advect:
 
     def __init__(self, f, grid: Grid, patch, ghost: int, dt: float, closure: str = "pmbc",
                  schedule: str = "auto", reduce_each_step: bool = False, graph: bool = False,
-                 history_cap: int = 0, stream=None, out_of_place: bool = False):
+                 history_cap: int = 0, stream=None, out_of_place: bool = False, runtime_shape: bool = False,
+                 slopes=None):
         import torch
         if not f.is_cuda or not f.is_contiguous():
             raise ValueError("f must be a contiguous device tensor")
@@ -226,8 +234,9 @@ class Advect:
             raise ValueError("f does not hold whole fields of this grid")
         nbatch = f.numel() // cube
         flags = ((CHASM_FLAG_REDUCE_EACH_STEP if reduce_each_step else 0) | (CHASM_FLAG_GRAPH if graph else 0)
-                 | (CHASM_FLAG_OUT_OF_PLACE if out_of_place else 0))
-        self.desc = make_desc(grid, patch, ghost, dt, dtype, closure, nbatch, flags, schedule, history_cap)
+                 | (CHASM_FLAG_OUT_OF_PLACE if out_of_place else 0)
+                 | (CHASM_FLAG_RUNTIME_SHAPE if runtime_shape else 0))
+        self.desc = make_desc(grid, patch, ghost, dt, dtype, closure, nbatch, flags, schedule, history_cap, slopes)
         self.f = f
         self.nbatch = nbatch
         self.grid = grid
@@ -279,8 +288,10 @@ def step_many(advects: Sequence[Advect], nsteps: Sequence[int]) -> None:
 
 def supported(grid: Grid, patch, ghost: int, dt: float = 0.0, dtype: str = "f32", closure: str = "pmbc",
               schedule: str = "auto") -> bool:
-    """True when the library has kernels for this grid / patch / ghost / dtype / closure
-    and schedule (asks the library's own descriptor validation; no device work)."""
+    """True when the library accepts this grid / patch / ghost / dtype / closure and
+    schedule (asks the library's own descriptor validation; no device work).  Every
+    valid descriptor is accepted with schedule 'auto' or 'plain' unless a resource
+    limit is hit; 'cube' and 'slab' need compiled kernels."""
     try:
         chasm_advect_workspace_bytes(make_desc(grid, patch, ghost, dt, dtype, closure, schedule=schedule))
         return True
@@ -290,7 +301,8 @@ def supported(grid: Grid, patch, ghost: int, dt: float = 0.0, dtype: str = "f32"
 
 def compiled_shapes(sizes=(8, 16, 24, 32, 48, 64)) -> list:
     """Every (dtype, N, M, ghost, closure) with compiled kernels, for cubic x-grids of N
-    nodes per axis (found through descriptor validation)."""
+    nodes per axis (found through descriptor validation: only compiled shapes offer the
+    SLAB schedule)."""
     out = []
     for n in sizes:
         grid = Grid((n, n, n), (0.0,) * 3, (float(n),) * 3, (1, 1, 1), (0.0,) * 3, (1.0,) * 3)
@@ -298,6 +310,6 @@ def compiled_shapes(sizes=(8, 16, 24, 32, 48, 64)) -> list:
             for cl in ("pmbc", "poly3", "neumann"):
                 for m in range(2, n + 1):
                     for g in range(1, n):
-                        if supported(grid, m, g, 0.0, dt, cl):
+                        if supported(grid, m, g, 0.0, dt, cl, "slab"):
                             out.append((dt, n, m, g, cl))
     return out

@@ -15,6 +15,7 @@
 #include "../../include/chasm_advect.h"
 #include "chasm_kernels.hpp"
 #include "chasm_registry.hpp"
+#include "chasm_rt.hpp"
 #include "chasm_tables.hpp"
 
 namespace chasm {
@@ -43,6 +44,30 @@ static const KernelSet* find_kernels(int dtype, int N, int M, int g, int closure
     for (const KernelSet* k : registry())
         if (k->dtype == dtype && k->N == N && k->M == M && k->G == g && k->CL == closure) return k;
     return nullptr;
+}
+
+// Marker of the runtime-shape kernels (chasm_rt.hpp): descriptors without compiled
+// kernels, the Hermite closure, or CHASM_FLAG_RUNTIME_SHAPE.
+static const KernelSet kRuntimeKernels = {};
+static bool is_rt(const KernelSet* ks) { return ks == &kRuntimeKernels; }
+
+// Geometry of the runtime-shape kernels for a descriptor (no tables).
+static RtJob rt_geometry(const chasm_advect_desc* d)
+{
+    RtJob j{};
+    j.nitems = (long long)d->nbatch * d->nk[0] * d->nk[1] * d->nk[2];
+    for (int a = 0; a < 3; ++a) {
+        j.nx[a] = d->nx[a];
+        j.nk[a] = d->nk[a];
+        RtAxis& A = j.ax[a];
+        A.N = d->nx[a];
+        A.M = d->patch[a] < d->nx[a] - 1 ? d->patch[a] : (d->nx[a] - 1 > 0 ? d->nx[a] - 1 : 1);
+        A.P = (A.N - 1 + A.M - 1) / A.M;
+        A.MLAST = A.N - 1 - (A.P - 1) * A.M;
+        A.G = d->ghost;
+        A.poly3 = d->closure == CHASM_CLOSURE_POLY3;
+    }
+    return j;
 }
 
 // ---------------------------------------------------------------------------
@@ -186,14 +211,18 @@ struct chasm_advect_s {
     bool rev_next = false;           // the next CUBE step of chasm_advect_step visits in reverse
     hipStream_t cap_stream = nullptr;
     bool poisoned = false;
+    // runtime-shape kernels: the job of each launch of a step (in place: all f -> f;
+    // out of place: f -> stage, stage -> stage, stage -> f)
+    bool rt = false;
+    RtJob rtj[3] = {};
 };
 
 static thread_local std::string g_err;
 
 namespace chasm {
-long long marginal_row(int N);
-hipError_t launch_marginals(int dtype, int N, const int nk[3], int nbatch, const double hx[3], const double hk[3],
-                            const void* f, double* part, double* out, hipStream_t st);
+long long marginal_row(const int nx[3]);
+hipError_t launch_marginals(int dtype, const int nx[3], const int nk[3], int nbatch, const double hx[3],
+                            const double hk[3], const void* f, double* part, double* out, hipStream_t st);
 
 // The other C entry points of the library (chasm_theta.h) report through the same
 // thread-local message.
@@ -227,35 +256,55 @@ static chasm_status validate(const chasm_advect_desc* d, const KernelSet** ks_ou
     if (d->ghost < 1) return fail(CHASM_EINVAL, "ghost must be >= 1");
     if (!std::isfinite(d->dt)) return fail(CHASM_EINVAL, "dt must be finite");
     if (d->dtype != CHASM_F32 && d->dtype != CHASM_F64) return fail(CHASM_EINVAL, "unknown dtype");
-    if (d->closure != CHASM_CLOSURE_PMBC && d->closure != CHASM_CLOSURE_POLY3 && d->closure != CHASM_CLOSURE_NEUMANN)
-        return fail(CHASM_EINVAL, "unknown closure");
+    if (d->closure < CHASM_CLOSURE_PMBC || d->closure > CHASM_CLOSURE_HERMITE) return fail(CHASM_EINVAL, "unknown closure");
     if (d->closure == CHASM_CLOSURE_POLY3 && d->ghost < 3) return fail(CHASM_EINVAL, "POLY3 closure needs ghost >= 3");
+    if (d->closure == CHASM_CLOSURE_HERMITE)
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(d->slope_lo[i]) || !std::isfinite(d->slope_hi[i]))
+                return fail(CHASM_EINVAL, "HERMITE closure needs finite end slopes");
     if (d->nbatch < 1) return fail(CHASM_EINVAL, "nbatch must be >= 1");
     if (d->schedule < CHASM_SCHED_AUTO || d->schedule > CHASM_SCHED_PLAIN) return fail(CHASM_EINVAL, "unknown schedule");
     if (d->history_cap < 0) return fail(CHASM_EINVAL, "history_cap must be >= 0");
-    if (d->flags & ~(uint32_t)(CHASM_FLAG_REDUCE_EACH_STEP | CHASM_FLAG_GRAPH | CHASM_FLAG_OUT_OF_PLACE))
+    if (d->flags & ~(uint32_t)(CHASM_FLAG_REDUCE_EACH_STEP | CHASM_FLAG_GRAPH | CHASM_FLAG_OUT_OF_PLACE |
+                               CHASM_FLAG_RUNTIME_SHAPE))
         return fail(CHASM_EINVAL, "unknown flags");
-    if (d->nx[0] != d->nx[1] || d->nx[0] != d->nx[2])
-        return fail(CHASM_EUNSUPPORTED, "kernels are built for equal nx on the three axes");
-    if (d->patch[0] != d->patch[1] || d->patch[0] != d->patch[2])
-        return fail(CHASM_EUNSUPPORTED, "kernels are built for equal patch sizes on the three axes");
-    const KernelSet* ks = find_kernels(d->dtype, d->nx[0], d->patch[0], d->ghost, d->closure);
-    if (!ks) {
-        char buf[160];
-        std::snprintf(buf, sizeof buf, "no kernel built for dtype=%d nx=%d patch=%d ghost=%d closure=%d", d->dtype,
-                      d->nx[0], d->patch[0], d->ghost, d->closure);
-        return fail(CHASM_EUNSUPPORTED, buf);
-    }
-    if (d->schedule == CHASM_SCHED_CUBE && !ks->cube)
-        return fail(CHASM_EUNSUPPORTED, "the x-cube does not fit in LDS for this nx and dtype");
     const double items = (double)d->nbatch * d->nk[0] * d->nk[1] * d->nk[2];
-    if (items * d->nx[0] > 2.0e9) return fail(CHASM_EUNSUPPORTED, "too many items for one launch grid");
+    const bool cubic = d->nx[0] == d->nx[1] && d->nx[0] == d->nx[2] && d->patch[0] == d->patch[1] &&
+                       d->patch[0] == d->patch[2];
+    const bool want_rt = (d->flags & CHASM_FLAG_RUNTIME_SHAPE) || d->closure == CHASM_CLOSURE_HERMITE;
+    const KernelSet* ks = (cubic && !want_rt) ? find_kernels(d->dtype, d->nx[0], d->patch[0], d->ghost, d->closure)
+                                              : nullptr;
+    if (ks) {
+        if (d->schedule == CHASM_SCHED_CUBE && !ks->cube)
+            return fail(CHASM_EUNSUPPORTED, "the x-cube does not fit in LDS for this nx and dtype");
+        if (items * d->nx[0] > 2.0e9) return fail(CHASM_EUNSUPPORTED, "too many items for one launch grid");
+    } else {
+        // the runtime-shape kernels: resource limits only
+        if (d->schedule == CHASM_SCHED_CUBE || d->schedule == CHASM_SCHED_SLAB)
+            return fail(CHASM_EUNSUPPORTED, "no compiled kernels for this shape: the runtime-shape kernels run the "
+                                            "PLAIN schedule (AUTO or PLAIN)");
+        const RtJob g = rt_geometry(d);
+        const int eb = d->dtype == CHASM_F64 ? 8 : 4;
+        for (int a = 0; a < 3; ++a) {
+            const int L = rt_lines_per_block(g, a, eb);
+            if (L == 0) {
+                char buf[200];
+                std::snprintf(buf, sizeof buf, "axis %d: a line of %d nodes with patches of %d cells exceeds the LDS "
+                              "tiles of the runtime-shape kernels", a + 1, d->nx[a], d->patch[a]);
+                return fail(CHASM_EUNSUPPORTED, buf);
+            }
+            const double lines = (double)d->nx[0] * d->nx[1] * d->nx[2] / d->nx[a];
+            if (items * std::ceil(lines / L) > 2.0e9) return fail(CHASM_EUNSUPPORTED, "too many blocks for one launch grid");
+        }
+        ks = &kRuntimeKernels;
+    }
     if (ks_out) *ks_out = ks;
     return CHASM_OK;
 }
 
 static int resolve_schedule(const chasm_advect_desc* d, const KernelSet* ks)
 {
+    if (is_rt(ks)) return CHASM_SCHED_PLAIN;
     if (d->schedule != CHASM_SCHED_AUTO) return d->schedule;
     return ks->cube ? CHASM_SCHED_CUBE : CHASM_SCHED_SLAB;
 }
@@ -265,6 +314,7 @@ static int resolve_schedule(const chasm_advect_desc* d, const KernelSet* ks)
 static long long step_partial_rows(const chasm_advect_desc* d, const KernelSet* ks, int sched)
 {
     const long long nkp = (long long)d->nk[0] * d->nk[1] * d->nk[2];
+    if (is_rt(ks)) return nkp * rt_rows_per_item(rt_geometry(d), d->dtype);
     if (sched == CHASM_SCHED_CUBE) return nkp * ks->cube_rows;
     if (sched == CHASM_SCHED_SLAB) return nkp * std::max(ks->pencil_rows, ks->slab_rows);
     return nkp * ks->pencil_rows;
@@ -276,6 +326,8 @@ static long long step_partial_rows(const chasm_advect_desc* d, const KernelSet* 
 struct TableBlock {
     std::vector<char> bytes;
     size_t off_w64[3], off_w32[3], off_shift[3];
+    // runtime-shape kernels: interface rows times h, end-slope bias times h, patch factors
+    size_t off_st64[3], off_st32[3], off_bi64[3], off_bi32[3], off_lu64[3], off_lu32[3];
 };
 
 template <typename V>
@@ -287,14 +339,25 @@ static size_t push(std::vector<char>& b, const V* p, size_t n)
     return off;
 }
 
+// FP64 vector and its FP32 mirror into the block.
+static void push_both(std::vector<char>& b, const std::vector<double>& v, size_t& off64, size_t& off32)
+{
+    off64 = push(b, v.data(), v.size());
+    const std::vector<float> f(v.begin(), v.end());
+    off32 = push(b, f.data(), f.size());
+}
+
 static bool build_tables(const chasm_advect_desc* d, const KernelSet* ks, TableBlock& tb, std::string& err)
 {
+    const bool rt = is_rt(ks);
+    const RtJob geo = rt_geometry(d);
     AxisTables at[3];
     for (int a = 0; a < 3; ++a) {
         const double h = (d->x_hi[a] - d->x_lo[a]) / d->nx[a];
         const double hk = (d->k_hi[a] - d->k_lo[a]) / d->nk[a];
-        if (!build_axis_tables(d->nx[a], d->patch[a], d->ghost, ks->G, h, d->closure, d->nk[a], d->k_lo[a], hk, d->dt,
-                               at[a], err))
+        const int M = rt ? geo.ax[a].M : d->patch[a];
+        if (!build_axis_tables(d->nx[a], M, d->ghost, rt ? d->ghost : ks->G, h, d->closure, d->nk[a], d->k_lo[a], hk,
+                               d->dt, at[a], err, d->slope_lo[a], d->slope_hi[a]))
             return false;
     }
     for (int a = 0; a < 3; ++a) {
@@ -302,6 +365,19 @@ static bool build_tables(const chasm_advect_desc* d, const KernelSet* ks, TableB
         std::vector<float> w32(at[a].w.begin(), at[a].w.end());
         tb.off_w32[a] = push(tb.bytes, w32.data(), w32.size());
         tb.off_shift[a] = push(tb.bytes, at[a].shift.data(), at[a].shift.size());
+        if (!rt) continue;
+        const AxisTables& t = at[a];
+        std::vector<double> st(t.stencil), bi(t.bias), lu((size_t)6 * (t.M + 1), 0.0);
+        for (double& x : st) x *= t.h;
+        for (double& x : bi) x *= t.h;
+        const int ms[2] = {t.M, t.MLAST};
+        for (int v = 0; v < 2; ++v) {
+            double* base = lu.data() + (size_t)v * 3 * (t.M + 1);
+            patch_factors(ms[v], base, base + (t.M + 1), base + 2 * (t.M + 1));
+        }
+        push_both(tb.bytes, st, tb.off_st64[a], tb.off_st32[a]);
+        push_both(tb.bytes, bi, tb.off_bi64[a], tb.off_bi32[a]);
+        push_both(tb.bytes, lu, tb.off_lu64[a], tb.off_lu32[a]);
     }
     return true;
 }
@@ -424,6 +500,14 @@ static hipError_t issue_passes(chasm_advect_t h, hipStream_t s, const int* kinds
 
 static hipError_t issue_step(chasm_advect_t h, hipStream_t s, bool rev = false)
 {
+    if (h->rt) {
+        const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
+        hipError_t e = hipSuccess;
+        for (int a = 0; a < 3 && e == hipSuccess; ++a)
+            e = rt_sweep(h->rtj[a], a, h->desc.dtype, (red && a == 2) ? h->partials : nullptr, s);
+        if (e == hipSuccess && red) e = launch_finalize(h, h->partial_rows, true, s);
+        return e;
+    }
     if (h->schedule == CHASM_SCHED_SLAB) {
         const int one[2] = {PASS_SLAB_A, PASS_PENCIL_1};
         return issue_passes(h, s, one, 2);
@@ -630,6 +714,28 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
         h->w_sf.jobs[0].f = h->stage;
         h->w_ss.jobs[0].f = h->w_ss.jobs[0].out = h->stage;
     }
+    if (is_rt(ks)) {
+        h->rt = true;
+        RtJob j = rt_geometry(desc);
+        for (int a = 0; a < 3; ++a) {
+            RtAxis& A = j.ax[a];
+            A.stencil = tbase + (f64 ? tb.off_st64[a] : tb.off_st32[a]);
+            A.bias = tbase + (f64 ? tb.off_bi64[a] : tb.off_bi32[a]);
+            A.lu = tbase + (f64 ? tb.off_lu64[a] : tb.off_lu32[a]);
+            A.shift = reinterpret_cast<const int*>(tbase + tb.off_shift[a]);
+            A.w = tbase + (f64 ? tb.off_w64[a] : tb.off_w32[a]);
+        }
+        for (int p = 0; p < 3; ++p) {
+            h->rtj[p] = j;
+            h->rtj[p].f = f_dev;
+            h->rtj[p].out = f_dev;
+        }
+        if (h->stage) {   // x1: f -> stage, x2: stage -> stage, x3: stage -> f
+            h->rtj[0].out = h->stage;
+            h->rtj[1].f = h->rtj[1].out = h->stage;
+            h->rtj[2].f = h->stage;
+        }
+    }
 
     if (desc->flags & CHASM_FLAG_GRAPH) {
         if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
@@ -734,8 +840,9 @@ chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const i
     hipStream_t s = n > 0 ? hs[0]->stream : nullptr;
     // Handles that record per-step diagnostics run their call on their own, exactly as
     // chasm_advect_step does.
+    auto alone = [](chasm_advect_t h) { return (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) || h->rt; };
     for (int32_t i = 0; i < n; ++i)
-        if (hs[i]->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) {
+        if (alone(hs[i])) {
             const chasm_status st = chasm_advect_step(hs[i], nsteps[i]);
             if (st != CHASM_OK) return st;
         }
@@ -751,7 +858,7 @@ chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const i
     };
     int32_t rounds = 0;
     for (int32_t i = 0; i < n; ++i)
-        if (!(hs[i]->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP))
+        if (!alone(hs[i]))
             rounds = std::max(rounds, hs[i]->schedule == CHASM_SCHED_SLAB && nsteps[i] > 0 ? nsteps[i] + 1 : nsteps[i]);
     std::vector<int32_t> live;
     std::vector<int> kinds;
@@ -759,7 +866,7 @@ chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const i
         live.clear();
         kinds.clear();
         for (int32_t i = 0; i < n; ++i) {
-            if (hs[i]->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) continue;
+            if (alone(hs[i])) continue;
             const int k = kind_at(i, r);
             if (k == -2) continue;
             live.push_back(i);
@@ -815,7 +922,8 @@ chasm_status chasm_advect_diagnostics(chasm_advect_t h, double* out)
 {
     if (!h || !out) return fail(CHASM_EINVAL, "NULL argument");
     if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
-    hipError_t e = h->ks->reduce(h->work, h->partials, h->stream);
+    hipError_t e = h->rt ? rt_reduce(h->rtj[0], h->desc.dtype, h->partials, h->stream)
+                         : h->ks->reduce(h->work, h->partials, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "reduce launch");
     const long long nkp = (long long)h->desc.nk[0] * h->desc.nk[1] * h->desc.nk[2];
     e = launch_finalize(h, nkp, false, h->stream);
@@ -871,7 +979,13 @@ chasm_status chasm_advect_diagnostics_noalloc(const chasm_advect_desc* desc, con
     }
     fin.vol = fin.hx[0] * fin.hx[1] * fin.hx[2] * fin.hk[0] * fin.hk[1] * fin.hk[2];
     // the same kernels and summation order as chasm_advect_diagnostics
-    e = ks->reduce(w, part, s);
+    if (is_rt(ks)) {
+        RtJob j = rt_geometry(desc);
+        j.f = f_dev;
+        e = rt_reduce(j, desc->dtype, part, s);
+    } else {
+        e = ks->reduce(w, part, s);
+    }
     if (e != hipSuccess) return fail(CHASM_EDEVICE, std::string("reduce launch: ") + hipGetErrorString(e));
     const double* src = part;
     long long rows = nkp;
@@ -892,11 +1006,12 @@ chasm_status chasm_advect_marginals(chasm_advect_t h, double* w1, double* w2, do
     if (!h) return fail(CHASM_EINVAL, "handle is NULL");
     if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
     const chasm_advect_desc& d = h->desc;
-    const int N = d.nx[0];
+    const int N0 = d.nx[0], N1 = d.nx[1], N2 = d.nx[2];
     const long long nitems = (long long)d.nk[0] * d.nk[1] * d.nk[2] * d.nbatch;
-    const long long per_b = (long long)N * (d.nk[0] + d.nk[1] + d.nk[2]) + (long long)N * N;
+    const long long per_b = (long long)N0 * d.nk[0] + (long long)N1 * d.nk[1] + (long long)N2 * d.nk[2] +
+                            (long long)N0 * N1;
     if (!h->marg_part) {
-        if (hipMalloc((void**)&h->marg_part, (size_t)nitems * marginal_row(N) * sizeof(double)) != hipSuccess)
+        if (hipMalloc((void**)&h->marg_part, (size_t)nitems * marginal_row(d.nx) * sizeof(double)) != hipSuccess)
             return fail(CHASM_ENOMEM, "hipMalloc(marginal rows) failed");
         if (hipMalloc((void**)&h->marg_out, (size_t)per_b * d.nbatch * sizeof(double)) != hipSuccess)
             return fail(CHASM_ENOMEM, "hipMalloc(marginals) failed");
@@ -906,13 +1021,14 @@ chasm_status chasm_advect_marginals(chasm_advect_t h, double* w1, double* w2, do
         hx[a] = (d.x_hi[a] - d.x_lo[a]) / d.nx[a];
         hk[a] = (d.k_hi[a] - d.k_lo[a]) / d.nk[a];
     }
-    hipError_t e = launch_marginals(d.dtype, N, d.nk, d.nbatch, hx, hk, h->f, h->marg_part, h->marg_out, h->stream);
+    hipError_t e = launch_marginals(d.dtype, d.nx, d.nk, d.nbatch, hx, hk, h->f, h->marg_part, h->marg_out, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "marginals launch");
     std::vector<double> all((size_t)per_b * d.nbatch);
     e = hipMemcpyAsync(all.data(), h->marg_out, all.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "marginals copy");
-    const size_t n1 = (size_t)N * d.nk[0], n2 = (size_t)N * d.nk[1], n3 = (size_t)N * d.nk[2], np = (size_t)N * N;
+    const size_t n1 = (size_t)N0 * d.nk[0], n2 = (size_t)N1 * d.nk[1], n3 = (size_t)N2 * d.nk[2],
+                 np = (size_t)N0 * N1;
     for (int b = 0; b < d.nbatch; ++b) {
         const double* src = all.data() + (size_t)b * per_b;
         if (w1) std::memcpy(w1 + b * n1, src, n1 * sizeof(double));

@@ -61,8 +61,51 @@ __global__ __launch_bounds__(NT) void k_marg_item(const T* __restrict__ f, doubl
     for (int c = threadIdx.x; c < N * N; c += NT) out[3 * N + c] = Q[c];
 }
 
+// Runtime-shape form of k_marg_item for any (n0, n1, n2): one block per item, the
+// same row layout (a[x1] | b[x2] | c[x3] | q[x2][x1]), fixed summation orders.
+// Columns q first (threads own (x1, x2) columns), then the x3-plane sums c (every
+// wave sums its columns of a plane, the waves' sums added in order), then a and b
+// from the stored q (the block's own global writes, visible after the barrier).
+template <typename T>
+__global__ __launch_bounds__(256) void k_marg_item_rt(const T* __restrict__ f, int n0, int n1, int n2,
+                                                      double* __restrict__ part)
+{
+    __shared__ double PW[4];
+    const long long plane = (long long)n0 * n1;
+    const long long item = blockIdx.x;
+    const long long ROW = (long long)n0 + n1 + n2 + plane;
+    const T* src = f + item * plane * n2;
+    double* out = part + item * ROW;
+    double* q = out + n0 + n1 + n2;
+    for (long long c = threadIdx.x; c < plane; c += 256) {
+        double acc = 0.0;
+        for (int z = 0; z < n2; ++z) acc += (double)src[z * plane + c];
+        q[c] = acc;
+    }
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    for (int z = 0; z < n2; ++z) {
+        double x = 0.0;
+        for (long long c = threadIdx.x; c < plane; c += 256) x += (double)src[z * plane + c];
+        for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (ln == 0) PW[wv] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) out[n0 + n1 + z] = PW[0] + PW[1] + PW[2] + PW[3];
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < n0; t += 256) {
+        double a = 0.0;
+        for (int y = 0; y < n1; ++y) a += q[(long long)y * n0 + t];
+        out[t] = a;
+    }
+    for (int t = threadIdx.x; t < n1; t += 256) {
+        double b = 0.0;
+        for (int x = 0; x < n0; ++x) b += q[(long long)t * n0 + x];
+        out[n0 + t] = b;
+    }
+}
+
 struct MargArgs {
-    int N, nk[3], nbatch;
+    int nx[3], nk[3], nbatch;
     double s[4];                 // cell volumes of the integrated variables: W1, W2, W3, P
 };
 
@@ -70,9 +113,9 @@ struct MargArgs {
 __global__ __launch_bounds__(256) void k_marg_sum(const double* __restrict__ part, MargArgs a,
                                                   double* __restrict__ out)
 {
-    const int N = a.N, n1 = a.nk[0], n2 = a.nk[1], n3 = a.nk[2];
-    const long long ROW = 3LL * N + (long long)N * N;
-    const long long per_b = (long long)N * (n1 + n2 + n3) + (long long)N * N;
+    const int N0 = a.nx[0], N1 = a.nx[1], N2 = a.nx[2], n1 = a.nk[0], n2 = a.nk[1], n3 = a.nk[2];
+    const long long ROW = (long long)N0 + N1 + N2 + (long long)N0 * N1;
+    const long long per_b = (long long)N0 * n1 + (long long)N1 * n2 + (long long)N2 * n3 + (long long)N0 * N1;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= per_b * a.nbatch) return;
     const int b = (int)(gid / per_b);
@@ -80,26 +123,26 @@ __global__ __launch_bounds__(256) void k_marg_sum(const double* __restrict__ par
     const double* base = part + (long long)b * n1 * n2 * n3 * ROW;
     auto item = [&](int k1, int k2, int k3) { return base + (((long long)k3 * n2 + k2) * n1 + k1) * ROW; };
     double s = 0.0, scale;
-    if (r < (long long)N * n1) {
-        const int k1 = (int)(r / N), x = (int)(r % N);
+    if (r < (long long)N0 * n1) {
+        const int k1 = (int)(r / N0), x = (int)(r % N0);
         for (int k3 = 0; k3 < n3; ++k3)
             for (int k2 = 0; k2 < n2; ++k2) s += item(k1, k2, k3)[x];
         scale = a.s[0];
-    } else if ((r -= (long long)N * n1) < (long long)N * n2) {
-        const int k2 = (int)(r / N), x = (int)(r % N);
+    } else if ((r -= (long long)N0 * n1) < (long long)N1 * n2) {
+        const int k2 = (int)(r / N1), x = (int)(r % N1);
         for (int k3 = 0; k3 < n3; ++k3)
-            for (int k1 = 0; k1 < n1; ++k1) s += item(k1, k2, k3)[N + x];
+            for (int k1 = 0; k1 < n1; ++k1) s += item(k1, k2, k3)[N0 + x];
         scale = a.s[1];
-    } else if ((r -= (long long)N * n2) < (long long)N * n3) {
-        const int k3 = (int)(r / N), x = (int)(r % N);
+    } else if ((r -= (long long)N1 * n2) < (long long)N2 * n3) {
+        const int k3 = (int)(r / N2), x = (int)(r % N2);
         for (int k2 = 0; k2 < n2; ++k2)
-            for (int k1 = 0; k1 < n1; ++k1) s += item(k1, k2, k3)[2 * N + x];
+            for (int k1 = 0; k1 < n1; ++k1) s += item(k1, k2, k3)[N0 + N1 + x];
         scale = a.s[2];
     } else {
-        r -= (long long)N * n3;                          // (x2, x1) = r
+        r -= (long long)N2 * n3;                         // (x2, x1) = r
         for (int k3 = 0; k3 < n3; ++k3)
             for (int k2 = 0; k2 < n2; ++k2)
-                for (int k1 = 0; k1 < n1; ++k1) s += item(k1, k2, k3)[3 * N + r];
+                for (int k1 = 0; k1 < n1; ++k1) s += item(k1, k2, k3)[N0 + N1 + N2 + r];
         scale = a.s[3];
     }
     out[gid] = s * scale;
@@ -113,42 +156,51 @@ static hipError_t launch_item(const void* f, long long nitems, double* part, hip
     return hipGetLastError();
 }
 
+// Item rows: the compiled form for the cubic grids it is built for, else the runtime one.
 template <typename T>
-static hipError_t launch_item_n(int N, const void* f, long long nitems, double* part, hipStream_t st)
+static hipError_t launch_item_n(const int nx[3], const void* f, long long nitems, double* part, hipStream_t st)
 {
-    switch (N) {
-        case 8: return launch_item<T, 8>(f, nitems, part, st);
-        case 16: return launch_item<T, 16>(f, nitems, part, st);
-        case 24: return launch_item<T, 24>(f, nitems, part, st);
-        case 32: return launch_item<T, 32>(f, nitems, part, st);
-        case 48: return launch_item<T, 48>(f, nitems, part, st);
-        case 64: return launch_item<T, 64>(f, nitems, part, st);
-        default: return hipErrorInvalidValue;
+    if (nx[0] == nx[1] && nx[0] == nx[2]) {
+        switch (nx[0]) {
+            case 8: return launch_item<T, 8>(f, nitems, part, st);
+            case 16: return launch_item<T, 16>(f, nitems, part, st);
+            case 24: return launch_item<T, 24>(f, nitems, part, st);
+            case 32: return launch_item<T, 32>(f, nitems, part, st);
+            case 48: return launch_item<T, 48>(f, nitems, part, st);
+            case 64: return launch_item<T, 64>(f, nitems, part, st);
+            default: break;
+        }
     }
+    hipLaunchKernelGGL((k_marg_item_rt<T>), dim3((unsigned)nitems), dim3(256), 0, st, static_cast<const T*>(f), nx[0],
+                       nx[1], nx[2], part);
+    return hipGetLastError();
 }
 
-// Rows of FP64 item partials the marginals need (3N + N^2 per item).
-long long marginal_row(int N) { return 3LL * N + (long long)N * N; }
+// Rows of FP64 item partials the marginals need (n0 + n1 + n2 + n0 n1 per item).
+long long marginal_row(const int nx[3]) { return (long long)nx[0] + nx[1] + nx[2] + (long long)nx[0] * nx[1]; }
 
-// Both passes on stream st: part holds nitems * marginal_row(N) doubles, out
-// nbatch * (N (nk1 + nk2 + nk3) + N^2) doubles.
-hipError_t launch_marginals(int dtype, int N, const int nk[3], int nbatch, const double hx[3], const double hk[3],
-                            const void* f, double* part, double* out, hipStream_t st)
+// Both passes on stream st: part holds nitems * marginal_row(nx) doubles, out
+// nbatch * (nx1 nk1 + nx2 nk2 + nx3 nk3 + nx1 nx2) doubles.
+hipError_t launch_marginals(int dtype, const int nx[3], const int nk[3], int nbatch, const double hx[3],
+                            const double hk[3], const void* f, double* part, double* out, hipStream_t st)
 {
     const long long nitems = (long long)nk[0] * nk[1] * nk[2] * nbatch;
-    hipError_t e = dtype == CHASM_F64 ? launch_item_n<double>(N, f, nitems, part, st)
-                                      : launch_item_n<float>(N, f, nitems, part, st);
+    hipError_t e = dtype == CHASM_F64 ? launch_item_n<double>(nx, f, nitems, part, st)
+                                      : launch_item_n<float>(nx, f, nitems, part, st);
     if (e != hipSuccess) return e;
     MargArgs a{};
-    a.N = N;
     a.nbatch = nbatch;
-    for (int d = 0; d < 3; ++d) a.nk[d] = nk[d];
+    for (int d = 0; d < 3; ++d) {
+        a.nx[d] = nx[d];
+        a.nk[d] = nk[d];
+    }
     const double v[3] = {hx[0] * hk[0], hx[1] * hk[1], hx[2] * hk[2]};
     a.s[0] = v[1] * v[2];
     a.s[1] = v[0] * v[2];
     a.s[2] = v[0] * v[1];
     a.s[3] = hx[2] * hk[0] * hk[1] * hk[2];
-    const long long total = ((long long)N * (nk[0] + nk[1] + nk[2]) + (long long)N * N) * nbatch;
+    const long long total = ((long long)nx[0] * nk[0] + (long long)nx[1] * nk[1] + (long long)nx[2] * nk[2] +
+                             (long long)nx[0] * nx[1]) * nbatch;
     hipLaunchKernelGGL(k_marg_sum, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, a, out);
     return hipGetLastError();
 }

@@ -78,6 +78,57 @@ bool neumann_slope_rows(int N, double h, const std::vector<int>& ifaces, std::ve
     return true;
 }
 
+// The Hermite condition of eq. 2.13 with given end slopes phi_L, phi_R: eliminating
+// eta_{-1} = eta_1 - 2h phi_L and eta_N = eta_{N-2} + 2h phi_R leaves
+// [4 2; 1 4 1; ...; 2 4] eta = 6 phi + 2h (phi_L e_0 - phi_R e_{N-1}).  The interface
+// slopes are then linear in (phi, phi_L, phi_R); their data part is the Neumann rows,
+// and eL[q], eR[q] are the coefficients of phi_L and phi_R (at the two line ends the
+// slope is the given one: eL = 1 at I = 0, eR = 1 at I = N-1).
+bool hermite_end_columns(int N, double h, const std::vector<int>& ifaces, std::vector<double>& eL,
+                         std::vector<double>& eR)
+{
+    if (N < 2 || !(h > 0.0)) return false;
+    std::vector<double> cp(N), den(N), y(N), eta(N + 2);
+    for (int i = 0; i < N; ++i) {
+        const double sub = i == N - 1 ? 2.0 : 1.0, sup = i == 0 ? 2.0 : 1.0;
+        den[i] = 4.0 - (i > 0 ? sub * cp[i - 1] : 0.0);
+        cp[i] = sup / den[i];
+    }
+    eL.assign(ifaces.size(), 0.0);
+    eR.assign(ifaces.size(), 0.0);
+    for (int side = 0; side < 2; ++side) {
+        // right-hand side of the unit end slope: 2h e_0 (left) or -2h e_{N-1} (right)
+        for (int i = 0; i < N; ++i) {
+            const double sub = i == N - 1 ? 2.0 : 1.0;
+            const double r = side == 0 ? (i == 0 ? 2.0 * h : 0.0) : (i == N - 1 ? -2.0 * h : 0.0);
+            y[i] = (r - (i > 0 ? sub * y[i - 1] : 0.0)) / den[i];
+        }
+        for (int i = N - 2; i >= 0; --i) y[i] -= cp[i] * y[i + 1];
+        for (int i = 0; i < N; ++i) eta[i + 1] = y[i];
+        eta[0] = eta[2] - 2.0 * h * (side == 0 ? 1.0 : 0.0);          // eta_{-1}
+        eta[N + 1] = eta[N - 1] + 2.0 * h * (side == 1 ? 1.0 : 0.0);  // eta_N
+        for (size_t q = 0; q < ifaces.size(); ++q) {
+            const int I = ifaces[q];
+            (side == 0 ? eL : eR)[q] = (eta[I + 2] - eta[I]) / (2.0 * h);
+        }
+    }
+    return true;
+}
+
+void patch_factors(int m, double* inv, double* ainv, double* cp)
+{
+    double prev = 0.0;
+    for (int i = 0; i <= m; ++i) {
+        const double a = (i == 0) ? 0.0 : (i == m ? 1.0 / 3.0 : 1.0 / 6.0);
+        const double c = (i == m) ? 0.0 : (i == 0 ? 1.0 / 3.0 : 1.0 / 6.0);
+        const double den = 2.0 / 3.0 - a * prev;
+        inv[i] = 1.0 / den;
+        ainv[i] = a / den;
+        cp[i] = c / den;
+        prev = cp[i];
+    }
+}
+
 // Minimum-norm correction of one stencil row so that it differentiates cubics
 // exactly: sum_j c_j (j-I)^q = delta_{q1}/h, q = 0..3.  With V_jq = ((j-I)/g)^q the
 // conditions read V^T c = e, e = (0, 1/(g h), 0, 0); the correction is
@@ -140,7 +191,7 @@ static void weights_eq38(double a, double b[4])
 }
 
 bool build_axis_tables(int N, int M, int g, int G, double h, int closure, int nk, double k_lo, double hk,
-                       double dt, AxisTables& out, std::string& err)
+                       double dt, AxisTables& out, std::string& err, double slope_lo, double slope_hi)
 {
     if (N < 2 || M < 1 || g < 1 || G < g || !(h > 0.0) || nk < 1) {
         err = "axis tables: bad shape";
@@ -158,7 +209,8 @@ bool build_axis_tables(int N, int M, int g, int G, double h, int closure, int nk
     std::vector<int> ifaces(P + 1);
     for (int q = 0; q <= P; ++q) ifaces[q] = q < P ? q * M : N - 1;
     std::vector<double> rows;
-    if (!(closure == 2 ? neumann_slope_rows(N, h, ifaces, rows) : natural_slope_rows(N, h, ifaces, rows))) {
+    const bool hermite_rows = closure == 2 || closure == 3;
+    if (!(hermite_rows ? neumann_slope_rows(N, h, ifaces, rows) : natural_slope_rows(N, h, ifaces, rows))) {
         err = "axis tables: global spline solve failed";
         return false;
     }
@@ -178,6 +230,21 @@ bool build_axis_tables(int N, int M, int g, int G, double h, int closure, int nk
         }
     }
 
+    out.bias.assign((size_t)(P + 1), 0.0);
+    if (closure == 3) {
+        std::vector<double> eL, eR;
+        if (!hermite_end_columns(N, h, ifaces, eL, eR)) {
+            err = "axis tables: Hermite end columns failed";
+            return false;
+        }
+        for (int q = 0; q <= P; ++q) {
+            const int I = ifaces[q];
+            // the given slopes sit one cell beyond the line ends (columns -1 and N):
+            // kept when within the ghost width of the interface
+            if (I + 1 <= g) out.bias[q] += eL[q] * slope_lo;
+            if (N - I <= g) out.bias[q] += eR[q] * slope_hi;
+        }
+    }
     out.shift.assign(nk, 0);
     out.w.assign((size_t)nk * 4, 0.0);
     for (int i = 0; i < nk; ++i) {

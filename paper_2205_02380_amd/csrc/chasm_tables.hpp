@@ -20,6 +20,7 @@ struct AxisTables {
     std::vector<double> stencil;   // (P+1)*(2G+1)
     std::vector<int> shift;        // nk
     std::vector<double> w;         // nk*4
+    std::vector<double> bias;      // P+1: slope part from the given end slopes (closure 3)
 };
 
 // Number of patches of M cells covering N nodes.
@@ -32,9 +33,19 @@ bool natural_slope_rows(int N, double h, const std::vector<int>& ifaces, std::ve
 // The same for the Neumann global spline (zero slopes at both ends).
 bool neumann_slope_rows(int N, double h, const std::vector<int>& ifaces, std::vector<double>& out);
 
+// Coefficients of the given end slopes in the interface slopes of the Hermite global
+// spline (eq. 2.13): eL[q] for phi_L, eR[q] for phi_R.
+bool hermite_end_columns(int N, double h, const std::vector<int>& ifaces, std::vector<double>& eL,
+                         std::vector<double>& eR);
+
+// Thomas factors of the reduced patch system of m+1 rows (see PatchLU in chasm_line.hpp):
+// inv, ainv, cp of length m+1.
+void patch_factors(int m, double* inv, double* ainv, double* cp);
+
 // Build every table of one axis.  closure: 0 paper PMBC, 1 cubic-exact variant,
-// 2 Neumann global spline.
+// 2 Neumann global spline, 3 Hermite global spline with end slopes slope_lo, slope_hi.
 bool build_axis_tables(int N, int M, int g, int G, double h, int closure, int nk, double k_lo, double hk,
-                       double dt, AxisTables& out, std::string& err);
+                       double dt, AxisTables& out, std::string& err, double slope_lo = 0.0,
+                       double slope_hi = 0.0);
 
 }  // namespace chasm

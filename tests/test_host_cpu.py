@@ -39,9 +39,11 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_desc_layout_matches_header():
-    # 3*4*2 ints, 12 doubles, 3 ints + ghost, dt, 4 int32/uint32, schedule, history_cap
+    # 3*4*2 ints, 12 doubles, 3 ints + ghost, dt, 4 int32/uint32, schedule, history_cap,
+    # 6 end-slope doubles
     d = chasm.chasm_advect_desc()
-    assert ctypes.sizeof(d) == 24 + 96 + 16 + 8 + 24
+    assert ctypes.sizeof(d) == 24 + 96 + 16 + 8 + 24 + 48
+    assert chasm.chasm_advect_desc.slope_lo.offset % 8 == 0
     assert chasm.chasm_advect_desc.dt.offset % 8 == 0
 
 
@@ -56,10 +58,12 @@ def test_desc_layout_matches_header():
     (lambda d: setattr(d, "flags", 1 << 9), chasm.CHASM_EINVAL),
     (lambda d: setattr(d, "dt", float("nan")), chasm.CHASM_EINVAL),
     (lambda d: (setattr(d, "closure", 1), setattr(d, "ghost", 2)), chasm.CHASM_EINVAL),
-    (lambda d: d.patch.__setitem__(0, 7), chasm.CHASM_EUNSUPPORTED),
-    (lambda d: d.nx.__setitem__(0, 20), chasm.CHASM_EUNSUPPORTED),
-    (lambda d: setattr(d, "ghost", 9), chasm.CHASM_EUNSUPPORTED),
-    (lambda d: setattr(d, "closure", 1), chasm.CHASM_EUNSUPPORTED),
+    (lambda d: setattr(d, "closure", 4), chasm.CHASM_EINVAL),
+    (lambda d: (setattr(d, "closure", 3), d.slope_lo.__setitem__(1, float("inf"))), chasm.CHASM_EINVAL),
+    # resource limits of the runtime-shape kernels, and schedules they do not provide
+    (lambda d: d.nx.__setitem__(0, 5000), chasm.CHASM_EUNSUPPORTED),
+    (lambda d: (d.patch.__setitem__(0, 7), setattr(d, "schedule", 2)), chasm.CHASM_EUNSUPPORTED),
+    (lambda d: (d.nx.__setitem__(1, 40), setattr(d, "schedule", 1)), chasm.CHASM_EUNSUPPORTED),
 ])
 def test_descriptor_validation(mutate, status):
     w = inputs.workload("C2")
@@ -69,6 +73,28 @@ def test_descriptor_validation(mutate, status):
         chasm.chasm_advect_workspace_bytes(d)
     assert ei.value.status == status
     assert chasm.chasm_advect_last_error()
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda d: d.patch.__setitem__(0, 7),                    # unequal patch lengths
+    lambda d: d.nx.__setitem__(0, 20),                      # unequal axes
+    lambda d: setattr(d, "ghost", 9),                       # no compiled (patch, ghost)
+    lambda d: setattr(d, "closure", 1),                     # no compiled POLY3 shape
+    lambda d: (d.nx.__setitem__(0, 61), d.nx.__setitem__(1, 61), d.nx.__setitem__(2, 61),
+               d.patch.__setitem__(0, 15), d.patch.__setitem__(1, 15), d.patch.__setitem__(2, 15),
+               setattr(d, "ghost", 15)),                    # the paper's 61-node, 4-patch line
+    lambda d: (d.nx.__setitem__(0, 40), d.nx.__setitem__(1, 48), d.nx.__setitem__(2, 36)),
+    lambda d: (setattr(d, "closure", 3), d.slope_lo.__setitem__(0, 0.25)),
+    lambda d: setattr(d, "flags", chasm.CHASM_FLAG_RUNTIME_SHAPE),
+])
+def test_any_valid_shape_is_accepted_by_the_runtime_kernels(mutate):
+    """Descriptors without compiled kernels run on the runtime-shape kernels (PLAIN)."""
+    w = inputs.workload("C2")
+    d = chasm.make_desc(w.grid, w.patch, w.ghost, w.dt)
+    mutate(d)
+    assert chasm.chasm_advect_workspace_bytes(d) > 0
+    d.schedule = chasm.CHASM_SCHED_PLAIN
+    assert chasm.chasm_advect_workspace_bytes(d) > 0
 
 
 def test_cube_schedule_rejected_when_cube_exceeds_lds():

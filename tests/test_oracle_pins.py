@@ -399,3 +399,76 @@ def test_neumann_stencils_end_rows_vanish_and_full_window_is_global():
     full = oracle.stencils(32, 8, 31, h, oracle.NEUMANN)
     errs = [np.max(np.abs(oracle.stencils(32, 8, g, h, oracle.NEUMANN) - full)) for g in (4, 6, 8)]
     assert errs[0] / errs[1] > 10 and errs[1] / errs[2] > 10
+
+
+# ---- the Hermite global condition with given end slopes (eq. 2.13) -----------------
+# The closure uses rows of the inverse of the global matrix whose boundary rows are
+# eq. 2.13 with right-hand sides phi_L, phi_R.  Untruncated it is the clamped cubic
+# spline with those end slopes; the slopes enter linearly; zero slopes give the Neumann
+# closure; the interface slopes at the two line ends are the given ones.
+from scipy.interpolate import CubicSpline as _CubicSpline
+
+
+@pytest.mark.parametrize("N,M", [(16, 5), (13, 4), (24, 8)])
+@pytest.mark.parametrize("alpha", [0.37, -0.81, 1.6, -2.2])
+def test_hermite_untruncated_is_scipy_clamped_spline(N, M, alpha):
+    h = 0.4
+    x = np.arange(N) * h
+    rng = np.random.default_rng(N + M)
+    phi = np.cos(0.7 * x) + rng.standard_normal(N) * 0.1
+    sl = (0.55, -1.3)
+    got = oracle.line_bc(N, M, N, h, alpha, phi, slopes=sl)
+    ref = _CubicSpline(x, phi, bc_type=((1, sl[0]), (1, sl[1])))(x - alpha * h)
+    inside = (x - alpha * h >= x[0]) & (x - alpha * h <= x[-1])
+    assert inside.sum() >= N // 2
+    assert np.max(np.abs(got[inside] - ref[inside])) < 1e-13
+    glob = oracle.global_line_hermite(N, h, alpha, phi, slopes=sl)
+    assert np.max(np.abs(glob[inside] - ref[inside])) < 1e-13
+
+
+def test_hermite_zero_slopes_is_the_neumann_closure():
+    N, M, g, h = 20, 6, 4, 0.3
+    phi = np.sin(np.arange(N) * 0.5)
+    for a in (0.2, -0.6, 1.3):
+        assert np.array_equal(oracle.line_bc(N, M, g, h, a, phi, slopes=(0.0, 0.0)),
+                              oracle.line(N, M, g, h, a, phi, closure=oracle.NEUMANN))
+
+
+def test_hermite_is_affine_in_the_end_slopes():
+    N, M, g, h, a = 18, 5, 4, 0.5, 0.45
+    rng = np.random.default_rng(3)
+    phi = rng.standard_normal(N)
+    sl = (0.8, -0.35)
+    both = oracle.line_bc(N, M, g, h, a, phi, slopes=sl)
+    data = oracle.line_bc(N, M, g, h, a, phi, slopes=(0.0, 0.0))
+    ends = oracle.line_bc(N, M, g, h, a, np.zeros(N), slopes=sl)
+    assert np.max(np.abs(both - data - ends)) < 1e-13
+    # doubling the slopes doubles their contribution
+    ends2 = oracle.line_bc(N, M, g, h, a, np.zeros(N), slopes=(2 * sl[0], 2 * sl[1]))
+    assert np.max(np.abs(ends2 - 2 * ends)) < 1e-13
+
+
+def test_hermite_end_interfaces_take_the_given_slopes():
+    N, M, g, h = 22, 7, 3, 0.25
+    sl = (1.7, -0.9)
+    c, bias = oracle.stencils_bc(N, M, g, h, oracle.HERMITE, sl)
+    assert abs(bias[0] - sl[0]) < 1e-13 and abs(bias[-1] - sl[1]) < 1e-13
+    assert np.max(np.abs(c[0])) < 1e-13 and np.max(np.abs(c[-1])) < 1e-13
+    # interior interfaces farther than g from both ends take no end-slope part
+    P = len(bias) - 1
+    for q in range(1, P):
+        I = q * M
+        if I + 1 > g and N - I > g:
+            assert bias[q] == 0.0
+
+
+def test_hermite_truncation_converges_to_the_global_spline():
+    N, M, h, a = 40, 8, 0.3, 0.55
+    x = np.arange(N) * h
+    phi = np.exp(-0.5 * (x - 6.0) ** 2) + 0.2 * x
+    sl = (0.2, 0.2)
+    ref = oracle.global_line_hermite(N, h, a, phi, slopes=sl)
+    errs = [np.max(np.abs(oracle.line_bc(N, M, g, h, a, phi, slopes=sl) - ref)) for g in (4, 6, 8, 10)]
+    for e0, e1 in zip(errs, errs[1:]):
+        assert e1 < e0 / 5          # ~|sqrt(3)-2|^-2 = 13.9 per +2 in g
+    assert np.max(np.abs(oracle.line_bc(N, M, N, h, a, phi, slopes=sl) - ref)) < 1e-13

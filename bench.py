@@ -377,19 +377,21 @@ def bench_theta(args):
 def bench_lpc1(args):
     """Full LPC1 steps of the Wigner-Coulomb equation (Sec. 2.2): the characteristic step
     and two truncated-kernel Theta_V evaluations per step.  Hydrogen (one proton at the
-    origin) on 64^3 x-nodes on [-9.6, 9.6)^3 (dx = 0.3, the paper's spacing) by 16^3
-    k-nodes on [-6.4, 6.4)^3 (dk = 0.8), patch 16, ghost 8, tau = 0.025, FP32 field."""
+    origin) on the paper's x-grid of Sec. 5.2: 61^3 nodes on [-9, 9]^3 (dx = 0.3, four
+    patches of 15 cells per axis, n_nb = 15; this line has no compiled kernels, so the
+    characteristic step runs on the runtime-shape kernels), by 16^3 k-nodes on
+    [-6.4, 6.4)^3 (dk = 0.8), tau = 0.025, FP32 field."""
     import torch
     from paper_2205_02380_amd import inputs, lpc1
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    grid = inputs.Grid((64,) * 3, (-9.6,) * 3, (9.6,) * 3, (16,) * 3, (-6.4,) * 3, (6.4,) * 3)
+    grid = inputs.Grid((61,) * 3, (-9.0,) * 3, (9.3,) * 3, (16,) * 3, (-6.4,) * 3, (6.4,) * 3)
     pk = inputs.random_packets(4, 31, c_range=(-3.0, 3.0), k0_range=(-1.0, 1.0), s_range=(0.8, 1.5))
     f = torch.empty(grid.shape(), dtype=torch.float32, device=dev)
     coef, gx, gk = inputs.packet_factors(grid, pk)
     inputs.fill_separable(f, coef, gx, gk)
     tau = 0.025
-    s = lpc1.LPC1(f, grid, 16, 8, tau, [(0.0, 0.0, 0.0)], stream=stream)
+    s = lpc1.LPC1(f, grid, 15, 15, tau, [(0.0, 0.0, 0.0)], stream=stream)
     settle(torch, dev)
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -419,8 +421,8 @@ def bench_lpc1(args):
         "value": grid.points * steps / total_s, "unit": "point-updates/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": total_s * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 field, f64 Theta", "data": "synthetic (seeded Gaussian-packet mixture)",
-        "config": {"workload": "lpc1: 64^3 x [-9.6,9.6)^3 by 16^3 k [-6.4,6.4)^3, 1,073,741,824 points, one proton, "
-                               "patch 16, ghost 8, tau 0.025"},
+        "config": {"workload": "lpc1: 61^3 x [-9,9]^3 (dx 0.3) by 16^3 k [-6.4,6.4)^3, 929,714,176 points, one "
+                               "proton, 4 patches of 15 cells, n_nb 15, tau 0.025"},
         "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
                             "mean": float(per.mean())},
         "roofline": {"bound": "alu", "achieved": flops / (float(per.mean()) / 1e3) / 1e12, "peak": 78.6,

@@ -15,7 +15,11 @@
  * The k-box Omega is the half-open grid box of side nk_d * hk_d; D is its diameter.
  * The library builds T and its transform on the host in FP64 once per handle and
  * evaluates the convolutions in FP64 on the device (FFT of period 2 nk per axis,
- * zero padded), whatever the storage type of the field.
+ * zero padded), whatever the storage type of the field.  For nk 8 and 16 one block
+ * holds an x-point's whole transform in LDS; for nk 32 and 64 (and on request 16) the
+ * staged form runs the transforms over batches of x-points with a complex FP64
+ * intermediate of 2 nk^3 values per x-point in device memory (at most about 2 GiB per
+ * handle, plus nk^3 doubles per x-point of the batch for more than one nucleus).
  *
  * Field layout: as in chasm_advect.h, f[b][k3][k2][k1][x3][x2][x1] (x1 fastest),
  * caller-owned contiguous device memory of float (CHASM_F32) or double (CHASM_F64).
@@ -40,8 +44,12 @@ extern "C" {
 
 typedef struct chasm_theta_s* chasm_theta_t;   /* opaque handle */
 
+/* Descriptor flags. */
+#define CHASM_THETA_FLAG_STAGED 1u   /* use the staged form (below) also where the one-block
+                                        form exists (nk 16) */
+
 typedef struct {
-    int32_t nx[3], nk[3];          /* grid nodes per axis; nk[0] = nk[1] = nk[2] in {8, 16} */
+    int32_t nx[3], nk[3];          /* grid nodes per axis; nk[0] = nk[1] = nk[2] in {8, 16, 32, 64} */
     double x_lo[3], x_hi[3];       /* half-open x box */
     double k_lo[3], k_hi[3];       /* half-open k box (Omega) */
     int32_t nnuc;                  /* 1 .. CHASM_THETA_MAX_NUCLEI */
@@ -49,11 +57,13 @@ typedef struct {
     double z_nuc[CHASM_THETA_MAX_NUCLEI];      /* charges z_a (1 for a proton) */
     int32_t dtype;                 /* chasm_dtype of the field and of the output */
     int32_t nbatch;                /* independent fields of this grid, leading dim b */
+    uint32_t flags;                /* CHASM_THETA_FLAG_* */
 } chasm_theta_desc;
 
 /* Create a handle: validates the descriptor (CHASM_EINVAL; CHASM_EUNSUPPORTED for
  * an nk without kernels), builds T and its transform in FP64 on the host, uploads the
- * transform and allocates one field-sized workspace (x-major copy).  hip_stream is a
+ * transform and allocates one field-sized workspace (x-major copy) and, for the staged
+ * form, its batch intermediate.  hip_stream is a
  * hipStream_t (NULL = default stream) used by every later call. */
 chasm_status chasm_theta_create(const chasm_theta_desc* desc, void* hip_stream, chasm_theta_t* out);
 

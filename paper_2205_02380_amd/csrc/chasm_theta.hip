@@ -13,6 +13,7 @@
 
 #include "../../include/chasm_theta.h"
 #include "chasm_theta.hpp"
+#include "chasm_theta_big.hpp"
 
 namespace chasm {
 
@@ -159,11 +160,16 @@ static void tensor_partial(const int nk[3], const std::vector<double>& T, std::v
 }
 
 // ---------------------------------------------------------------------------
-// Compiled kernels: (storage type, nk) -> chunk count R and block size.
+// Compiled kernels: (storage type, nk) -> chunk count R and block size of the one-block
+// form (nk 8, 16), and the staged form over batches of x-points (nk 16, 32, 64).
+using BigFn = hipError_t (*)(void* fx, const double* kt, const ThetaArgs& a, fft::cd* W, double* acc,
+                             long long total, long long X, hipStream_t s);
+
 struct ThetaKernels {
     int dtype, nk;
     hipError_t (*theta)(void* fx, const double* kt, const ThetaArgs& a, long long total, hipStream_t s);
     hipError_t (*transpose)(const void* in, void* out, long long rows, long long cols, int batch, hipStream_t s);
+    BigFn big;                 // staged form (nullptr: none)
 };
 
 template <typename K>
@@ -186,6 +192,27 @@ static hipError_t launch_theta(void* fx, const double* kt, const ThetaArgs& a, l
     return hipGetLastError();
 }
 
+// Staged form: x-points in batches of X; per batch and nucleus the three stages.
+template <typename T, int NK>
+static hipError_t launch_big(void* fx, const double* kt, const ThetaArgs& a, fft::cd* W, double* acc,
+                             long long total, long long X, hipStream_t s)
+{
+    using B = BigShape<NK>;
+    for (long long x0 = 0; x0 < total; x0 += X) {
+        const long long nb = total - x0 < X ? total - x0 : X;
+        for (int nu = 0; nu < a.nnuc; ++nu) {
+            hipLaunchKernelGGL((k_thA<T, NK>), dim3((unsigned)(nb * B::BPX)), dim3(64), 0, s,
+                               static_cast<const T*>(fx), W, a, x0, nu);
+            hipLaunchKernelGGL((k_thBCD<NK>), dim3((unsigned)(nb * B::P)), dim3(B::NTB), 0, s, W, kt);
+            hipLaunchKernelGGL((k_thE<T, NK>), dim3((unsigned)(nb * B::BPX)), dim3(64), 0, s, W, acc,
+                               static_cast<T*>(fx), a, x0, nu, nu == 0 ? 1 : 0, nu == a.nnuc - 1 ? 1 : 0);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
 template <typename T>
 static hipError_t launch_transpose(const void* in, void* out, long long rows, long long cols, int batch, hipStream_t s)
 {
@@ -196,10 +223,14 @@ static hipError_t launch_transpose(const void* in, void* out, long long rows, lo
 }
 
 static const ThetaKernels kThetaKernels[] = {
-    {CHASM_F32, 8, launch_theta<float, 8, 1, 256>, launch_transpose<float>},
-    {CHASM_F64, 8, launch_theta<double, 8, 1, 256>, launch_transpose<double>},
-    {CHASM_F32, 16, launch_theta<float, 16, 4, 256>, launch_transpose<float>},
-    {CHASM_F64, 16, launch_theta<double, 16, 4, 256>, launch_transpose<double>},
+    {CHASM_F32, 8, launch_theta<float, 8, 1, 256>, launch_transpose<float>, nullptr},
+    {CHASM_F64, 8, launch_theta<double, 8, 1, 256>, launch_transpose<double>, nullptr},
+    {CHASM_F32, 16, launch_theta<float, 16, 4, 256>, launch_transpose<float>, launch_big<float, 16>},
+    {CHASM_F64, 16, launch_theta<double, 16, 4, 256>, launch_transpose<double>, launch_big<double, 16>},
+    {CHASM_F32, 32, nullptr, launch_transpose<float>, launch_big<float, 32>},
+    {CHASM_F64, 32, nullptr, launch_transpose<double>, launch_big<double, 32>},
+    {CHASM_F32, 64, nullptr, launch_transpose<float>, launch_big<float, 64>},
+    {CHASM_F64, 64, nullptr, launch_transpose<double>, launch_big<double, 64>},
 };
 
 static const ThetaKernels* find_theta(int dtype, int nk)
@@ -207,6 +238,21 @@ static const ThetaKernels* find_theta(int dtype, int nk)
     for (const ThetaKernels& k : kThetaKernels)
         if (k.dtype == dtype && k.nk == nk) return &k;
     return nullptr;
+}
+
+// Staged form: x-points per batch (intermediate W of X * 2 nk^3 complex values, at most
+// about 2 GiB) and whether a handle uses it.
+static long long big_batch(int nk, long long total)
+{
+    const long long per = 2LL * nk * nk * nk * 16;
+    long long X = (2LL << 30) / per;
+    if (X < 1) X = 1;
+    return X < total ? X : total;
+}
+
+static bool use_big(const chasm_theta_desc* d, const ThetaKernels* ks)
+{
+    return !ks->theta || (d->flags & CHASM_THETA_FLAG_STAGED);
 }
 
 }  // namespace chasm
@@ -219,6 +265,10 @@ struct chasm_theta_s {
     const ThetaKernels* ks = nullptr;
     double* kt = nullptr;               // kernel transformed along k1, k2 (tensor_partial)
     void* ws = nullptr;
+    bool big = false;                   // staged form
+    long long X = 0;                    // x-points per batch of the staged form
+    fft::cd* W = nullptr;               // its complex intermediate
+    double* acc = nullptr;              // its sum over nuclei (more than one nucleus)
     ThetaArgs args{};
     long long npts = 0, nkp = 0;
     bool poisoned = false;
@@ -250,10 +300,13 @@ static chasm_status validate(const chasm_theta_desc* d, const ThetaKernels** ks)
     if (d->nbatch < 1) return tfail(CHASM_EINVAL, "nbatch must be >= 1");
     const long long pts = (long long)d->nx[0] * d->nx[1] * d->nx[2] * d->nk[0] * d->nk[1] * d->nk[2];
     if (pts <= 0 || pts > (1LL << 40) / d->nbatch) return tfail(CHASM_EINVAL, "grid too large");
+    if (d->flags & ~(uint32_t)CHASM_THETA_FLAG_STAGED) return tfail(CHASM_EINVAL, "unknown flags");
     if (d->nk[0] != d->nk[1] || d->nk[1] != d->nk[2])
         return tfail(CHASM_EUNSUPPORTED, "kernels are built for equal nk on the three axes");
     const ThetaKernels* k = find_theta(d->dtype, d->nk[0]);
-    if (!k) return tfail(CHASM_EUNSUPPORTED, "no kernel for this nk (built: 8, 16)");
+    if (!k) return tfail(CHASM_EUNSUPPORTED, "no kernel for this nk (built: 8, 16, 32, 64)");
+    if ((d->flags & CHASM_THETA_FLAG_STAGED) && !k->big)
+        return tfail(CHASM_EUNSUPPORTED, "the staged form is built for nk 16, 32, 64");
     if (ks) *ks = k;
     return CHASM_OK;
 }
@@ -278,6 +331,12 @@ chasm_status chasm_theta_workspace_bytes(const chasm_theta_desc* desc, size_t* b
     const size_t pts = (size_t)desc->nx[0] * desc->nx[1] * desc->nx[2] * desc->nk[0] * desc->nk[1] * desc->nk[2];
     const size_t P3 = (size_t)8 * desc->nk[0] * desc->nk[1] * desc->nk[2];
     *bytes = pts * desc->nbatch * es + P3 * sizeof(double) + 512;
+    if (use_big(desc, ks)) {
+        const long long nk = desc->nk[0];
+        const long long X = big_batch((int)nk, (long long)desc->nx[0] * desc->nx[1] * desc->nx[2] * desc->nbatch);
+        *bytes += (size_t)X * 2 * nk * nk * nk * 16 + 256;
+        if (desc->nnuc > 1) *bytes += (size_t)X * nk * nk * nk * 8 + 256;
+    }
     return CHASM_OK;
 }
 
@@ -335,6 +394,15 @@ chasm_status chasm_theta_create(const chasm_theta_desc* desc, void* hip_stream, 
     const size_t es = desc->dtype == CHASM_F64 ? 8 : 4;
     if (hipMalloc(&h->ws, (size_t)h->npts * h->nkp * desc->nbatch * es) != hipSuccess)
         return bail(CHASM_ENOMEM, "hipMalloc(workspace) failed");
+    h->big = use_big(desc, ks);
+    if (h->big) {
+        const long long nkk = nk[0];
+        h->X = big_batch(nk[0], h->npts * desc->nbatch);
+        if (hipMalloc((void**)&h->W, (size_t)h->X * 2 * nkk * nkk * nkk * sizeof(fft::cd)) != hipSuccess)
+            return bail(CHASM_ENOMEM, "hipMalloc(staged intermediate) failed");
+        if (desc->nnuc > 1 && hipMalloc((void**)&h->acc, (size_t)h->X * nkk * nkk * nkk * sizeof(double)) != hipSuccess)
+            return bail(CHASM_ENOMEM, "hipMalloc(staged accumulator) failed");
+    }
     if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(CHASM_EDEVICE, "stream synchronize failed");
 
     ThetaArgs& a = h->args;
@@ -361,7 +429,9 @@ chasm_status chasm_theta_apply(chasm_theta_t h, const void* f_dev, void* out_dev
     if (h->poisoned) return tfail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
     const int nb = h->desc.nbatch;
     hipError_t e = h->ks->transpose(f_dev, h->ws, h->nkp, h->npts, nb, h->stream);
-    if (e == hipSuccess) e = h->ks->theta(h->ws, h->kt, h->args, h->npts * nb, h->stream);
+    if (e == hipSuccess)
+        e = h->big ? h->ks->big(h->ws, h->kt, h->args, h->W, h->acc, h->npts * nb, h->X, h->stream)
+                   : h->ks->theta(h->ws, h->kt, h->args, h->npts * nb, h->stream);
     if (e == hipSuccess) e = h->ks->transpose(h->ws, out_dev, h->npts, h->nkp, nb, h->stream);
     if (e != hipSuccess) {
         h->poisoned = true;
@@ -376,6 +446,8 @@ chasm_status chasm_theta_destroy(chasm_theta_t h)
     if (h->stream) hipStreamSynchronize(h->stream);
     if (h->kt) hipFree(h->kt);
     if (h->ws) hipFree(h->ws);
+    if (h->W) hipFree(h->W);
+    if (h->acc) hipFree(h->acc);
     delete h;
     return CHASM_OK;
 }

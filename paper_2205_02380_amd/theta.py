@@ -30,7 +30,11 @@ class chasm_theta_desc(ctypes.Structure):
         ("z_nuc", ctypes.c_double * MAX_NUCLEI),
         ("dtype", ctypes.c_int32),
         ("nbatch", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
     ]
+
+
+FLAG_STAGED = 1
 
 
 EXPORTS = ("chasm_theta_create", "chasm_theta_apply", "chasm_theta_workspace_bytes", "chasm_theta_tensor",
@@ -62,7 +66,7 @@ def _check(st: int) -> None:
 
 
 def make_desc(grid: Grid, nuclei: Sequence[Sequence[float]], charges: Optional[Sequence[float]] = None,
-              dtype: str = "f32", nbatch: int = 1) -> chasm_theta_desc:
+              dtype: str = "f32", nbatch: int = 1, staged: bool = False) -> chasm_theta_desc:
     d = chasm_theta_desc()
     for a in range(3):
         d.nx[a], d.nk[a] = int(grid.nx[a]), int(grid.nk[a])
@@ -78,6 +82,7 @@ def make_desc(grid: Grid, nuclei: Sequence[Sequence[float]], charges: Optional[S
         d.z_nuc[i] = float(z)
     d.dtype = {"f32": chasm.CHASM_F32, "f64": chasm.CHASM_F64}[dtype]
     d.nbatch = int(nbatch)
+    d.flags = FLAG_STAGED if staged else 0
     return d
 
 
@@ -113,10 +118,11 @@ class Theta:
     """out = Theta_V^T[f] for V = -sum_a z_a / |x - x_a|, on fields of ``grid``
     (torch device tensors [b][k3][k2][k1][x3][x2][x1] or without b)."""
 
-    def __init__(self, grid: Grid, nuclei, charges=None, dtype: str = "f32", nbatch: int = 1, stream=None):
+    def __init__(self, grid: Grid, nuclei, charges=None, dtype: str = "f32", nbatch: int = 1, stream=None,
+                 staged: bool = False):
         import torch
         self.grid = grid
-        self.desc = make_desc(grid, nuclei, charges, dtype, nbatch)
+        self.desc = make_desc(grid, nuclei, charges, dtype, nbatch, staged)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.h = chasm_theta_create(self.desc, self.stream.cuda_stream)
         self.nbatch = nbatch

@@ -75,3 +75,17 @@ def test_lpc1_rejects_mismatched_descriptors():
     with pytest.raises(chasm.ChasmError):
         s.step(-1)
     s.close()
+
+
+def test_lpc1_on_a_runtime_shape_grid():
+    """An anisotropic x-grid without compiled advection kernels: the LPC1 step's
+    characteristic step runs on the runtime-shape kernels."""
+    grid = inputs.Grid((9, 7, 6), (-3.0, -2.5, -2.0), (3.0, 2.5, 2.0), (8, 8, 8), (-2.4,) * 3, (2.4,) * 3)
+    f0 = field(grid, 8)
+    f = torch.tensor(f0, dtype=torch.float64, device=DEV)
+    print("lpc1 runtime-shape grid 9x7x6, nk=8, 2 steps", flush=True)
+    with lpc1.LPC1(f, grid, (4, 3, 5), 3, 0.05, [(0.2, -0.1, 0.3)], [1.0]) as s:
+        s.step(2)
+    torch.cuda.synchronize()
+    ref = olpc1.lpc1(f0, grid, (4, 3, 5), 3, 0.05, 2, [(0.2, -0.1, 0.3)], [1.0])
+    assert np.max(np.abs(f.cpu().numpy() - ref)) < 1e-11 * np.max(np.abs(ref))

@@ -17,7 +17,8 @@ def grid(nx=4, nk=8, L=6.4):
 
 def test_desc_layout():
     d = theta.chasm_theta_desc()
-    assert ctypes.sizeof(d) == 264
+    assert ctypes.sizeof(d) == 272
+    assert theta.chasm_theta_desc.flags.offset == 264
     assert theta.chasm_theta_desc.x_nuc.offset == 128
     assert theta.chasm_theta_desc.dtype.offset == 256
 

@@ -315,14 +315,16 @@ def theta_flops_per_xpoint(nk: int) -> float:
 
 
 def bench_theta(args):
-    """Theta_V^T (Sec. 4) on the paper's N_k = 16 grid of Sec. 5.2: 61^3 x-nodes on
-    [-9, 9]^3 by 16^3 k-nodes on [-6.4, 6.4)^3, one nucleus at the origin, FP32 field,
-    FP64 arithmetic."""
+    """Theta_V^T (Sec. 4) on the paper's x-grid of Sec. 5.2: 61^3 x-nodes on [-9, 9]^3 by
+    N_k^3 k-nodes on [-6.4, 6.4)^3 (N_k = 16: dk = 0.8, the paper's grid; N_k = 32 refines
+    dk on the same k-box and runs the staged transforms), one nucleus at the
+    origin, FP32 field, FP64 arithmetic."""
     import torch
     from paper_2205_02380_amd import inputs, theta
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    grid = inputs.Grid((61,) * 3, (-9.0,) * 3, (9.3,) * 3, (16,) * 3, (-6.4,) * 3, (6.4,) * 3)
+    nk = args.nk
+    grid = inputs.Grid((61,) * 3, (-9.0,) * 3, (9.3,) * 3, (nk,) * 3, (-6.4,) * 3, (6.4,) * 3)
     pk = inputs.random_packets(4, 21, c_range=(-3.0, 3.0), k0_range=(-1.0, 1.0), s_range=(0.8, 1.5))
     f = torch.empty(grid.shape(), dtype=torch.float32, device=dev)
     coef, gx, gk = inputs.packet_factors(grid, pk)
@@ -343,33 +345,35 @@ def bench_theta(args):
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     total_s = ev[0].elapsed_time(ev[steps]) / 1e3
     npts = grid.cube
-    flops = theta_flops_per_xpoint(16) * npts
+    flops = theta_flops_per_xpoint(nk) * npts
     mean_s = float(per.mean()) / 1e3
     cpu = None
     if not args.no_cpu:
         from oracle import tkm
         rng = np.random.default_rng(23)
-        xidx = np.stack([rng.integers(0, 61, 16) for _ in range(3)], axis=1)
+        xidx = np.stack([rng.integers(0, 61, {16: 16, 32: 4}[nk]) for _ in range(3)], axis=1)
         fx = [f[:, :, :, i3, i2, i1].double().cpu().numpy() for i1, i2, i3 in xidx]
         t0 = time.perf_counter()
         for n, (i1, i2, i3) in enumerate(xidx):
             tkm.theta_point(fx[n], (grid.x_axis(0)[i1], grid.x_axis(1)[i2], grid.x_axis(2)[i3]), grid.k_lo, grid.hk)
         tc = time.perf_counter() - t0
         cpu = {"value": len(xidx) * grid.nkpts / tc, "unit": "point-evaluations/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(xidx)} seeded x-points x 4096 k-points ({tc:.1f} s, numpy FP64, threefold transforms)"}
+               "sample": f"{len(xidx)} seeded x-points x {grid.nkpts} k-points ({tc:.1f} s, numpy FP64, threefold "
+                         "transforms)"}
     th.close()
+    kern = "whole apply (transpose, k_theta, transpose)" if nk <= 16 else "whole apply (k_thA, k_thBCD, k_thE)"
     return {
         "metric": "Theta_V^T point-evaluations/s (truncated kernel method, FP64 arithmetic)",
         "value": grid.points * steps / total_s, "unit": "point-evaluations/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": total_s * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 (f32 field)", "data": "synthetic (seeded Gaussian-packet mixture)",
-        "config": {"workload": "theta: 61^3 x [-9,9]^3 by 16^3 k [-6.4,6.4)^3, 929,714,176 points, one nucleus, "
-                               "FP32 field, FP64 transforms"},
+        "config": {"workload": f"theta: 61^3 x [-9,9]^3 by {nk}^3 k [-6.4,6.4)^3, {grid.points:,} points, one "
+                               "nucleus, FP32 field, FP64 transforms"},
         "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
                             "mean": float(per.mean())},
         "roofline": {"bound": "alu", "achieved": flops / mean_s / 1e12, "peak": 78.6, "unit": "TFLOP/s",
                      "frac": flops / mean_s / 1e12 / 78.6, "traffic": None,
-                     "kernel": "whole apply (transpose, k_theta, transpose)", "flop_count": THETA_FLOP_NOTE},
+                     "kernel": kern, "flop_count": THETA_FLOP_NOTE},
         "cpu_baseline": cpu,
     }
 
@@ -379,13 +383,15 @@ def bench_lpc1(args):
     and two truncated-kernel Theta_V evaluations per step.  Hydrogen (one proton at the
     origin) on the paper's x-grid of Sec. 5.2: 61^3 nodes on [-9, 9]^3 (dx = 0.3, four
     patches of 15 cells per axis, n_nb = 15; this line has no compiled kernels, so the
-    characteristic step runs on the runtime-shape kernels), by 16^3 k-nodes on
-    [-6.4, 6.4)^3 (dk = 0.8), tau = 0.025, FP32 field."""
+    characteristic step runs on the runtime-shape kernels), by N_k^3 k-nodes on
+    [-6.4, 6.4)^3 (N_k = 16: dk = 0.8; N_k = 32: dk = 0.4, staged Theta_V), tau = 0.025,
+    FP32 field."""
     import torch
     from paper_2205_02380_amd import inputs, lpc1
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    grid = inputs.Grid((61,) * 3, (-9.0,) * 3, (9.3,) * 3, (16,) * 3, (-6.4,) * 3, (6.4,) * 3)
+    nk = args.nk
+    grid = inputs.Grid((61,) * 3, (-9.0,) * 3, (9.3,) * 3, (nk,) * 3, (-6.4,) * 3, (6.4,) * 3)
     pk = inputs.random_packets(4, 31, c_range=(-3.0, 3.0), k0_range=(-1.0, 1.0), s_range=(0.8, 1.5))
     f = torch.empty(grid.shape(), dtype=torch.float32, device=dev)
     coef, gx, gk = inputs.packet_factors(grid, pk)
@@ -405,24 +411,25 @@ def bench_lpc1(args):
     s.close()
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     total_s = ev[0].elapsed_time(ev[steps]) / 1e3
-    flops = 2 * theta_flops_per_xpoint(16) * grid.cube
+    flops = 2 * theta_flops_per_xpoint(nk) * grid.cube
     cpu = None
     if not args.no_cpu:
         from oracle import lpc1 as olpc1
-        small = inputs.Grid((8,) * 3, (-1.2,) * 3, (1.2,) * 3, (16,) * 3, (-6.4,) * 3, (6.4,) * 3)
+        sx = 8 if nk == 16 else 4
+        small = inputs.Grid((sx,) * 3, (-0.15 * sx,) * 3, (0.15 * sx,) * 3, (nk,) * 3, (-6.4,) * 3, (6.4,) * 3)
         f0 = inputs.gaussian_field(small, pk).numpy()
         t0 = time.perf_counter()
-        olpc1.lpc1(f0, small, 4, 3, tau, 1, [(0.0, 0.0, 0.0)], [1.0], direct=False)
+        olpc1.lpc1(f0, small, sx // 2, sx // 2 - 1, tau, 1, [(0.0, 0.0, 0.0)], [1.0], direct=False)
         tc = time.perf_counter() - t0
         cpu = {"value": small.points / tc, "unit": "point-updates/s", "cores": 1, "kind": "oracle",
-               "sample": f"one LPC1 step of an 8^3 x 16^3 grid ({small.points} points, {tc:.1f} s; numpy/C FP64)"}
+               "sample": f"one LPC1 step of a {sx}^3 x {nk}^3 grid ({small.points} points, {tc:.1f} s; numpy/C FP64)"}
     return {
         "metric": "LPC1 point-updates/s (Wigner-Coulomb step: advection + 2 truncated-kernel Theta_V)",
         "value": grid.points * steps / total_s, "unit": "point-updates/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": total_s * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 field, f64 Theta", "data": "synthetic (seeded Gaussian-packet mixture)",
-        "config": {"workload": "lpc1: 61^3 x [-9,9]^3 (dx 0.3) by 16^3 k [-6.4,6.4)^3, 929,714,176 points, one "
-                               "proton, 4 patches of 15 cells, n_nb 15, tau 0.025"},
+        "config": {"workload": f"lpc1: 61^3 x [-9,9]^3 (dx 0.3) by {nk}^3 k [-6.4,6.4)^3, {grid.points:,} points, "
+                               "one proton, 4 patches of 15 cells, n_nb 15, tau 0.025"},
         "step_latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99)),
                             "mean": float(per.mean())},
         "roofline": {"bound": "alu", "achieved": flops / (float(per.mean()) / 1e3) / 1e12, "peak": 78.6,
@@ -519,6 +526,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", default="C4", choices=["C2", "C3", "C4", "serving", "theta", "lpc1", "ho2d"])
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--nk", type=int, default=16, choices=[16, 32],
+                    help="k-nodes per axis of the theta and lpc1 workloads (61^3 x 64^3 FP32 is 238 GB a field)")
     ap.add_argument("--cpu-steps", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain device copy of 1 GiB (the reference for HBM counter scaling)")

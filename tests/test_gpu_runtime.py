@@ -1,6 +1,7 @@
 """GPU parity of the runtime-shape kernels (any per-axis nodes, patch length and ghost
 width; tables read from device memory) against the FP64 oracle: the paper's own line
 (61 nodes, 4 patches of 15 cells, n_nb = 15; Sec. 5.2-5.5), anisotropic and odd grids,
+one to ten patches per line and patches of 3 to 70 cells (both kernel forms),
 every closure including the Hermite condition with given end slopes (eq. 2.13), shifts
 of every class (|alpha| up to 1.4), FP32 and FP64; per-step FP64 diagnostics, graph
 replay, out-of-place runs, batches, marginals and the allocation-free diagnostics on
@@ -43,6 +44,13 @@ CASES = [  # (name, nx, nk, patch, ghost, closure, slopes, dt)
     ("hermite 24x18x30", (24, 18, 30), (2, 3, 2), (7, 5, 8), 5, "hermite",
      ((0.02, -0.03), (0.0, 0.05), (-0.04, 0.01)), 0.1),
     ("shifts beyond one cell", (26, 20, 16), (4, 3, 2), (6, 5, 4), 4, "pmbc", None, 0.35),
+    # patches of 17..64 cells (register arrays of 64), two patches, one patch per line
+    ("long patches 50x33x20", (50, 33, 20), (2, 2, 3), (24, 16, 19), 8, "neumann", None, 0.1),
+    # the paper's patch and ghost width on other lines: 2, 3 and 5 patches, a short last
+    # patch, and shifts of up to 18 cells (beyond the padded tile of the unrolled form)
+    ("patches of 15, n_nb 15, long shifts", (46, 31, 70), (2, 3, 2), (15, 15, 15), 15, "pmbc", None, 2.3),
+    # the general kernel: patches of more than 64 cells, more than 8 patches per line
+    ("wide and many patches 140x41x8", (140, 41, 8), (2, 2, 2), (70, 4, 7), 6, "pmbc", None, 0.1),
 ]
 
 

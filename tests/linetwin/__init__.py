@@ -32,10 +32,14 @@ _lib = None
 def load():
     global _lib
     if _lib is None:
-        newest = max(os.path.getmtime(p) for p in (SRC, TABLES, LINE))
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
-            build()
-        L = ctypes.CDLL(LIB)
+        # CHASM_LINETWIN_LIB: a build of the same sources made elsewhere (the sanitizer run)
+        path = os.environ.get("CHASM_LINETWIN_LIB")
+        if not path:
+            path = LIB
+            newest = max(os.path.getmtime(p) for p in (SRC, TABLES, LINE))
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < newest:
+                build()
+        L = ctypes.CDLL(path)
         pd = ctypes.POINTER(ctypes.c_double)
         L.twin_line.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double] * 3 + [pd, pd]
         L.twin_rows.argtypes = [ctypes.c_int] * 4 + [pd]

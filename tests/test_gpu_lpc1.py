@@ -89,3 +89,22 @@ def test_lpc1_on_a_runtime_shape_grid():
     torch.cuda.synchronize()
     ref = olpc1.lpc1(f0, grid, (4, 3, 5), 3, 0.05, 2, [(0.2, -0.1, 0.3)], [1.0])
     assert np.max(np.abs(f.cpu().numpy() - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_lpc1_nk32_staged_theta_on_the_paper_patch_line():
+    """N_k = 32 (the staged Theta_V) on an x-grid of 16 x 2 x 2 nodes whose first axis
+    has the paper's patch and ghost width (one patch of 15 cells, n_nb = 15: the unrolled
+    runtime-shape form), one step, FP64, against the oracle (threefold transforms)."""
+    grid = inputs.Grid((16, 2, 2), (-2.4, -0.3, -0.3), (2.4, 0.3, 0.3), (32, 32, 32), (-6.4,) * 3, (6.4,) * 3)
+    f0 = field(grid, 9)
+    f = torch.tensor(f0, dtype=torch.float64, device=DEV)
+    nuclei = [(0.35, 0.05, -0.1)]
+    print("lpc1 16x2x2 x 32^3, one step", flush=True)
+    with lpc1.LPC1(f, grid, (15, 1, 1), 15, 0.025, nuclei, [1.0]) as s:
+        s.step(1)
+    torch.cuda.synchronize()
+    print("  oracle", flush=True)
+    ref = olpc1.lpc1(f0, grid, (15, 1, 1), 15, 0.025, 1, nuclei, [1.0], direct=False)
+    err = float(np.max(np.abs(f.cpu().numpy() - ref)) / np.max(np.abs(ref)))
+    print(f"  rel err {err:.2e}", flush=True)
+    assert err < 1e-11

@@ -69,3 +69,43 @@ def test_inflow_modes_differ_only_at_inflow_nodes():
             assert np.array_equal(z[i, 1:], e[i, 1:])
         else:
             assert np.array_equal(z[i], e[i]) and np.allclose(z[i], f[i], rtol=0, atol=1e-13)
+
+
+def _one_step_matrix(nx, x_lo, hx, nk, k_lo, hk, M, g, omega, tau, inflow):
+    """The LPC1 step of the oracle as a matrix on the state f[k][x] (row-major): with
+    A the characteristic step (block-diagonal over k) and Th = omega diag(x) d_k, the
+    predictor-corrector is A + tau/2 (Th A + A Th) + tau^2/2 Th A Th."""
+    x, k = ho2d.axes(nx, x_lo, hx, nk, k_lo, hk)
+    n = nx * nk
+    A = np.zeros((n, n))
+    eye = np.eye(nx)
+    for i, kv in enumerate(k):
+        cols = ho2d.advect(eye, x, np.full(nx, kv), hx, M, g, tau, inflow=inflow)   # row j: image of e_j
+        A[i * nx:(i + 1) * nx, i * nx:(i + 1) * nx] = cols.T
+    D = ho2d.dk_spectral(np.eye(nk), hk)
+    Th = omega * np.kron(D, np.diag(x))
+    return A + 0.5 * tau * (Th @ A + A @ Th) + 0.5 * tau * tau * (Th @ A @ Th), x
+
+
+def test_extrapolated_inflow_admits_a_growing_boundary_mode_zero_inflow_does_not():
+    """Spectrum of the one-step operator on the paper's x-line (241 nodes on [-12, 12],
+    4 patches of 60 cells, n_nb = 20) and step (tau = 2e-5), k on [-6.4, 6.4) with
+    N_k = 8 (the paper's k-box, coarse enough for a dense eigensolve).  Ghost-
+    extrapolated inflow has a complex pair of growing modes (rate log|lambda|/tau of
+    about 0.59 per unit time, rising with N_k: 0.98 at 16, 1.61 at 32) peaked at the
+    x = +-12 boundary columns; with zero inflow every eigenvalue has |lambda| <= 1 to
+    rounding.  Both schemes share the periodic spectral k-derivative, so the growth
+    comes from the extrapolating inflow closure."""
+    rates = {}
+    for inflow in ("extrapolate", "zero"):
+        L, x = _one_step_matrix(241, -12.0, 0.1, 8, -6.4, 1.6, 60, 20, W, 2e-5, inflow)
+        lam, V = np.linalg.eig(L)
+        r = np.log(np.abs(lam)) / 2e-5
+        top = int(np.argmax(r))
+        rates[inflow] = r[top]
+        if inflow == "extrapolate":
+            amp = np.abs(V[:, top]).reshape(8, 241).max(axis=0)
+            assert abs(abs(x[int(np.argmax(amp))]) - 12.0) < 1e-9     # peaked at a boundary column
+            assert np.sum(np.isclose(r, r[top], rtol=1e-6)) == 2       # a complex-conjugate pair
+    assert 0.5 < rates["extrapolate"] < 0.7
+    assert rates["zero"] < 1e-8

@@ -121,7 +121,7 @@ def settle(torch, dev, seconds=0.4, nbytes=1 << 28):
     return n
 
 
-def settle_advect(torch, dev, f, g, patch, ghost, dt, schedule, seconds=0.4, out_of_place=False):
+def settle_advect(torch, dev, f, g, patch, ghost, dt, schedule, seconds=0.4, out_of_place=False, tile=0):
     """Run the same advection kernels on a scratch copy of the field for about `seconds`:
     an idle GPU, or one that ran other kernels, runs the first tens of milliseconds of
     this kernel a few percent slower.  The copy holds the field's own values (an all-zero
@@ -130,7 +130,8 @@ def settle_advect(torch, dev, f, g, patch, ghost, dt, schedule, seconds=0.4, out
     run."""
     from paper_2205_02380_amd import chasm
     scratch = f.clone()
-    adv = chasm.Advect(scratch, g, patch, ghost, dt, schedule=schedule, graph=True, out_of_place=out_of_place)
+    adv = chasm.Advect(scratch, g, patch, ghost, dt, schedule=schedule, graph=True, out_of_place=out_of_place,
+                       tile=tile)
     n = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
@@ -198,14 +199,17 @@ def bench_large(args, name):
                             log=lambda m: print(m, file=sys.stderr, flush=True))
         b = res["best"]
         tuning = {"best": b, "candidates": len(res["candidates"]),
-                  "table": [[c["patch"], c["ghost"], c["schedule"], c["out_of_place"], round(c["ms_per_step"], 3),
-                             float("%.3g" % c["deviation"])] for c in res["candidates"]]}
+                  "table_columns": ["patch", "ghost", "schedule", "tile", "out_of_place", "ms_per_step", "deviation"],
+                  "table": [[c["patch"], c["ghost"], c["schedule"], c["tile"], c["out_of_place"],
+                             round(c["ms_per_step"], 3), float("%.3g" % c["deviation"])] for c in res["candidates"]]}
         w = dataclasses.replace(w, patch=(b["patch"],) * 3, ghost=b["ghost"])
         sched = b["schedule"]
         oop = b["out_of_place"]
+        tile = b["tile"]
     else:
         sched = "auto"
         oop = False                 # measured on C4: in place 26.8 ms per step, out of place 27.5
+        tile = 0
     g = w.grid
     f = torch.empty(g.shape(), dtype=torch.float32, device=dev)
     coef, gx, gk = inputs.packet_factors(g, w.packets)
@@ -216,9 +220,9 @@ def bench_large(args, name):
     lat = min(steps, args.latency_steps)
     nall = args.warmup + steps + lat
     adv = chasm.Advect(f, g, w.patch, w.ghost, w.dt, schedule=sched, graph=True, reduce_each_step=True,
-                       history_cap=nall, stream=stream, out_of_place=oop)
+                       history_cap=nall, stream=stream, out_of_place=oop, tile=tile)
     sched = adv.schedule
-    settled = settle_advect(torch, dev, f, g, w.patch, w.ghost, w.dt, sched, out_of_place=oop)
+    settled = settle_advect(torch, dev, f, g, w.patch, w.ghost, w.dt, sched, out_of_place=oop, tile=tile)
     adv.step(args.warmup)
     total_s = time_steps(adv, torch, steps, stream)
     per = step_latencies(adv, torch, lat, stream)

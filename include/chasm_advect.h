@@ -105,8 +105,18 @@ enum {
     /* Use the runtime-shape kernels even where compiled kernels exist for the shape
      * (every descriptor the compiled kernels do not cover uses them anyway): one launch
      * per axis sweep with the tables read from device memory, the PLAIN schedule. */
-    CHASM_FLAG_RUNTIME_SHAPE = 1u << 3
+    CHASM_FLAG_RUNTIME_SHAPE = 1u << 3,
+    /* Bits 4-5: launch-shape variant of the compiled SLAB and PLAIN passes (the
+     * autotuner's tile-shape axis), CHASM_FLAG_TILE(t) for t = 0 (default), 1 (twice
+     * the x3-slabs per slab block, 128 lines per pencil block) or 2 (default slab block,
+     * 384 or 512 lines per pencil block).  Variants 1 and 2 exist for the FP32 shapes
+     * with nx = 48 or 64 and need the SLAB or PLAIN schedule named explicitly (else
+     * CHASM_EUNSUPPORTED).  The arithmetic does not depend on the variant: results are
+     * bitwise equal. */
+    CHASM_FLAG_TILE_SHIFT = 4,
+    CHASM_FLAG_TILE_MASK = 3u << 4
 };
+#define CHASM_FLAG_TILE(t) ((uint32_t)(t) << CHASM_FLAG_TILE_SHIFT)
 
 typedef struct {
     int32_t nx[3];            /* x nodes per axis (>= 2); grids with equal nx and patch on the

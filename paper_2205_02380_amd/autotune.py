@@ -1,8 +1,9 @@
-"""Autotuner: pick patch size, ghost width, kernel schedule and field placement for a
-grid.
+"""Autotuner: pick patch size, ghost width, kernel schedule, tile shape and field
+placement for a grid.
 
-Every candidate (patch M, ghost g, schedule, in place or out of place through a second
-field) that has compiled kernels is timed on the
+Every candidate (patch M, ghost g, schedule, tile shape -- the launch-shape variant of
+the SLAB and PLAIN passes: x3-slabs per slab block and lines per pencil block --, in
+place or out of place through a second field) that has compiled kernels is timed on the
 workload's own field (HIP events around graph-replayed steps) and its result after the
 tuning steps is compared with the most accurate candidate (the largest ghost width,
 then the largest patch): the PMBC truncation error shrinks like |sqrt3 - 2|^g, so a
@@ -27,25 +28,29 @@ from . import chasm, inputs
 
 
 def candidates(grid: inputs.Grid, dt: float, patches: Sequence[int], ghosts: Sequence[int],
-               schedules: Sequence[str], placements: Sequence[bool] = (False, True)) -> List[dict]:
+               schedules: Sequence[str], placements: Sequence[bool] = (False, True),
+               tiles: Sequence[int] = chasm.TILES) -> List[dict]:
+    """Every (patch, ghost, schedule, tile, placement) the library accepts for the grid
+    (its own descriptor validation decides; tile variants exist for some shapes only)."""
     out = []
     for M in patches:
         for g in ghosts:
             for sc in schedules:
-                d = chasm.make_desc(grid, M, g, dt, schedule=sc)
-                try:
-                    chasm.chasm_advect_workspace_bytes(d)
-                except chasm.ChasmError:
-                    continue
-                for oop in placements:
-                    out.append({"patch": M, "ghost": g, "schedule": sc, "out_of_place": oop})
+                for tile in tiles:
+                    d = chasm.make_desc(grid, M, g, dt, schedule=sc, flags=chasm.CHASM_FLAG_TILE(tile))
+                    try:
+                        chasm.chasm_advect_workspace_bytes(d)
+                    except chasm.ChasmError:
+                        continue
+                    for oop in placements:
+                        out.append({"patch": M, "ghost": g, "schedule": sc, "tile": tile, "out_of_place": oop})
     return out
 
 
 def accuracy_order(c: dict):
     """Most accurate first: largest ghost width, then largest patch; in place before out
     of place (equal results, less memory)."""
-    return (-c["ghost"], -c["patch"], c["schedule"], c["out_of_place"])
+    return (-c["ghost"], -c["patch"], c["schedule"], c["out_of_place"], c.get("tile", 0))
 
 
 def choose(cands: List[dict], margin: float = 0.01) -> dict:
@@ -60,12 +65,12 @@ def choose(cands: List[dict], margin: float = 0.01) -> dict:
 
 
 def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 16), ghosts=(4, 6, 8),
-         schedules=("cube", "slab", "plain"), placements=(False, True), steps: int = 5, warmup: int = 2,
-         tol: float = 1e-5, margin: float = 0.01, device: str = "cuda:0", log=None) -> dict:
+         schedules=("cube", "slab", "plain"), placements=(False, True), tiles=chasm.TILES, steps: int = 5,
+         warmup: int = 2, tol: float = 1e-5, margin: float = 0.01, device: str = "cuda:0", log=None) -> dict:
     import torch
     dev = torch.device(device)
     stream = torch.cuda.current_stream(dev)
-    cands = candidates(grid, dt, patches, ghosts, schedules, placements)
+    cands = candidates(grid, dt, patches, ghosts, schedules, placements, tiles)
     if not cands:
         raise ValueError("no compiled kernels for this grid")
     f0 = torch.empty(grid.shape(), dtype=torch.float32, device=dev)
@@ -79,7 +84,7 @@ def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 
     for c in cands:
         work.copy_(f0)
         adv = chasm.Advect(work, grid, c["patch"], c["ghost"], dt, schedule=c["schedule"], graph=True,
-                           stream=stream, out_of_place=c["out_of_place"])
+                           stream=stream, out_of_place=c["out_of_place"], tile=c["tile"])
         adv.step(warmup)
         torch.cuda.synchronize()
         work.copy_(f0)
@@ -99,7 +104,8 @@ def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 
             c["deviation"] = float((work - ref).abs().max()) / scale
         c["ok"] = c["deviation"] <= tol
         if log:
-            log(f"  M={c['patch']:2d} g={c['ghost']} {c['schedule']:5s} {'oop' if c['out_of_place'] else 'inp'} "
+            log(f"  M={c['patch']:2d} g={c['ghost']} {c['schedule']:5s} t{c['tile']} "
+                f"{'oop' if c['out_of_place'] else 'inp'} "
                 f"{c['ms_per_step']:8.3f} ms/step "
                 f"dev={c['deviation']:.2e}{'' if c['ok'] else '  (over tol)'}")
     del work, f0, ref

@@ -25,6 +25,13 @@ CHASM_F32, CHASM_F64 = 0, 1
 CHASM_CLOSURE_PMBC, CHASM_CLOSURE_POLY3, CHASM_CLOSURE_NEUMANN, CHASM_CLOSURE_HERMITE = 0, 1, 2, 3
 CHASM_SCHED_AUTO, CHASM_SCHED_CUBE, CHASM_SCHED_SLAB, CHASM_SCHED_PLAIN = 0, 1, 2, 3
 CHASM_FLAG_REDUCE_EACH_STEP, CHASM_FLAG_GRAPH, CHASM_FLAG_OUT_OF_PLACE, CHASM_FLAG_RUNTIME_SHAPE = 1, 2, 4, 8
+CHASM_FLAG_TILE_SHIFT, CHASM_FLAG_TILE_MASK = 4, 3 << 4
+TILES = (0, 1, 2)
+
+
+def CHASM_FLAG_TILE(t: int) -> int:
+    """Launch-shape variant t of the compiled SLAB and PLAIN passes (0 default)."""
+    return int(t) << CHASM_FLAG_TILE_SHIFT
 
 SCHEDULES = {"auto": 0, "cube": 1, "slab": 2, "plain": 3}
 SCHEDULE_NAMES = {v: k for k, v in SCHEDULES.items()}
@@ -217,12 +224,13 @@ def chasm_advect_version() -> str:
 class Advect:
     """A handle advancing ``f`` (a contiguous CUDA/HIP torch tensor of shape
     [b][k3][k2][k1][x3][x2][x1] or without b); every step ends in ``f``.  With
-    ``out_of_place`` the sweeps go through a second, library-owned field."""
+    ``out_of_place`` the sweeps go through a second, library-owned field; ``tile``
+    selects the launch-shape variant of the SLAB and PLAIN passes (FP32 48^3 / 64^3)."""
 
     def __init__(self, f, grid: Grid, patch, ghost: int, dt: float, closure: str = "pmbc",
                  schedule: str = "auto", reduce_each_step: bool = False, graph: bool = False,
                  history_cap: int = 0, stream=None, out_of_place: bool = False, runtime_shape: bool = False,
-                 slopes=None):
+                 slopes=None, tile: int = 0):
         import torch
         if not f.is_cuda or not f.is_contiguous():
             raise ValueError("f must be a contiguous device tensor")
@@ -235,7 +243,7 @@ class Advect:
         nbatch = f.numel() // cube
         flags = ((CHASM_FLAG_REDUCE_EACH_STEP if reduce_each_step else 0) | (CHASM_FLAG_GRAPH if graph else 0)
                  | (CHASM_FLAG_OUT_OF_PLACE if out_of_place else 0)
-                 | (CHASM_FLAG_RUNTIME_SHAPE if runtime_shape else 0))
+                 | (CHASM_FLAG_RUNTIME_SHAPE if runtime_shape else 0) | CHASM_FLAG_TILE(tile))
         self.desc = make_desc(grid, patch, ghost, dt, dtype, closure, nbatch, flags, schedule, history_cap, slopes)
         self.f = f
         self.nbatch = nbatch
@@ -287,13 +295,14 @@ def step_many(advects: Sequence[Advect], nsteps: Sequence[int]) -> None:
 
 
 def supported(grid: Grid, patch, ghost: int, dt: float = 0.0, dtype: str = "f32", closure: str = "pmbc",
-              schedule: str = "auto") -> bool:
+              schedule: str = "auto", tile: int = 0) -> bool:
     """True when the library accepts this grid / patch / ghost / dtype / closure and
     schedule (asks the library's own descriptor validation; no device work).  Every
     valid descriptor is accepted with schedule 'auto' or 'plain' unless a resource
     limit is hit; 'cube' and 'slab' need compiled kernels."""
     try:
-        chasm_advect_workspace_bytes(make_desc(grid, patch, ghost, dt, dtype, closure, schedule=schedule))
+        chasm_advect_workspace_bytes(make_desc(grid, patch, ghost, dt, dtype, closure,
+                                               flags=CHASM_FLAG_TILE(tile), schedule=schedule))
         return True
     except ChasmError:
         return False

@@ -22,28 +22,44 @@ namespace chasm {
 
 // ---------------------------------------------------------------------------
 // Kernel registry: every compiled (dtype, N, M, G).
-#define CHASM_DECL(T, N, M, G, CL) extern template const KernelSet* kernel_set<T, N, M, G, CL>();
+#define CHASM_DECL(T, N, M, G, CL) extern template const KernelSet* kernel_set<T, N, M, G, CL, 0>();
 CHASM_SHAPES(CHASM_DECL)
 #undef CHASM_DECL
+#define CHASM_DECL_TILES(T, N, M, G, CL)                                  \
+    extern template const KernelSet* kernel_set<T, N, M, G, CL, 1>();      \
+    extern template const KernelSet* kernel_set<T, N, M, G, CL, 2>();
+CHASM_TILED_SHAPES(CHASM_DECL_TILES)
+#undef CHASM_DECL_TILES
 
 static const std::vector<const KernelSet*>& registry()
 {
     static const std::vector<const KernelSet*> all = [] {
         std::vector<const KernelSet*> v;
-#define CHASM_REG(T, N, M, G, CL) v.push_back(kernel_set<T, N, M, G, CL>());
+#define CHASM_REG(T, N, M, G, CL) v.push_back(kernel_set<T, N, M, G, CL, 0>());
         CHASM_SHAPES(CHASM_REG)
 #undef CHASM_REG
+#define CHASM_REG_TILES(T, N, M, G, CL)                \
+    v.push_back(kernel_set<T, N, M, G, CL, 1>());      \
+    v.push_back(kernel_set<T, N, M, G, CL, 2>());
+        CHASM_TILED_SHAPES(CHASM_REG_TILES)
+#undef CHASM_REG_TILES
         return v;
     }();
     return all;
 }
 
 // The compiled kernels of (dtype, N, M, g, closure), or nullptr.
-static const KernelSet* find_kernels(int dtype, int N, int M, int g, int closure)
+static const KernelSet* find_kernels(int dtype, int N, int M, int g, int closure, int tile)
 {
     for (const KernelSet* k : registry())
-        if (k->dtype == dtype && k->N == N && k->M == M && k->G == g && k->CL == closure) return k;
+        if (k->dtype == dtype && k->N == N && k->M == M && k->G == g && k->CL == closure && k->tile == tile)
+            return k;
     return nullptr;
+}
+
+static int desc_tile(const chasm_advect_desc* d)
+{
+    return (int)((d->flags & CHASM_FLAG_TILE_MASK) >> CHASM_FLAG_TILE_SHIFT);
 }
 
 // Marker of the runtime-shape kernels (chasm_rt.hpp): descriptors without compiled
@@ -266,14 +282,23 @@ static chasm_status validate(const chasm_advect_desc* d, const KernelSet** ks_ou
     if (d->schedule < CHASM_SCHED_AUTO || d->schedule > CHASM_SCHED_PLAIN) return fail(CHASM_EINVAL, "unknown schedule");
     if (d->history_cap < 0) return fail(CHASM_EINVAL, "history_cap must be >= 0");
     if (d->flags & ~(uint32_t)(CHASM_FLAG_REDUCE_EACH_STEP | CHASM_FLAG_GRAPH | CHASM_FLAG_OUT_OF_PLACE |
-                               CHASM_FLAG_RUNTIME_SHAPE))
+                               CHASM_FLAG_RUNTIME_SHAPE | CHASM_FLAG_TILE_MASK))
         return fail(CHASM_EINVAL, "unknown flags");
+    const int tile = desc_tile(d);
+    if (tile >= kTiles) return fail(CHASM_EINVAL, "unknown tile variant");
     const double items = (double)d->nbatch * d->nk[0] * d->nk[1] * d->nk[2];
     const bool cubic = d->nx[0] == d->nx[1] && d->nx[0] == d->nx[2] && d->patch[0] == d->patch[1] &&
                        d->patch[0] == d->patch[2];
     const bool want_rt = (d->flags & CHASM_FLAG_RUNTIME_SHAPE) || d->closure == CHASM_CLOSURE_HERMITE;
-    const KernelSet* ks = (cubic && !want_rt) ? find_kernels(d->dtype, d->nx[0], d->patch[0], d->ghost, d->closure)
-                                              : nullptr;
+    const KernelSet* ks = (cubic && !want_rt)
+                              ? find_kernels(d->dtype, d->nx[0], d->patch[0], d->ghost, d->closure, tile)
+                              : nullptr;
+    if (tile > 0) {
+        if (!ks)
+            return fail(CHASM_EUNSUPPORTED, "tile variants exist only for compiled FP32 48^3 and 64^3 shapes");
+        if (d->schedule == CHASM_SCHED_CUBE || d->schedule == CHASM_SCHED_AUTO)
+            return fail(CHASM_EUNSUPPORTED, "a tile variant needs the SLAB or PLAIN schedule named");
+    }
     if (ks) {
         if (d->schedule == CHASM_SCHED_CUBE && !ks->cube)
             return fail(CHASM_EUNSUPPORTED, "the x-cube does not fit in LDS for this nx and dtype");

@@ -9,8 +9,15 @@ namespace chasm {
 // LDS available to one work-group on gfx950.
 constexpr size_t kLdsBytes = 160 * 1024;
 
-template <typename T, int N>
+// Launch shapes of (T, N) for tile variant TILE (the autotuner's tile-shape axis; the
+// kernels' arithmetic per line does not depend on it, so results are bitwise equal):
+//   0  the defaults below;
+//   1  twice the x3-slabs per slab block, 128 lines per pencil block;
+//   2  the default slab block, 384 (N = 48) or 512 (N = 64) lines per pencil block.
+// Variants 1 and 2 are compiled for the FP32 48^3 and 64^3 shapes only.
+template <typename T, int N, int TILE = 0>
 struct Launch {
+    static_assert(TILE == 0 || N == 48 || N == 64, "tile variants exist for N = 48 and 64");
     // Whole x-cube in LDS (rows padded to N+1) plus the block-sum scratch.
     static constexpr bool cube_fits = (size_t)N * N * (N + 1) * sizeof(T) + 1024 <= kLdsBytes;
     // threads per cube block: a multiple of N whose planes-per-round NT/N divide N;
@@ -18,9 +25,11 @@ struct Launch {
     static constexpr int cube_nt =
         N <= 8 ? 64 : (N <= 16 ? 256 : (N <= 24 ? (sizeof(T) == 4 ? 576 : 192) : 1024));
     // x3-slabs per slab block: S*N threads, a multiple of 64, S | N.
-    static constexpr int slab_s = N == 8 ? 8 : (N == 16 ? 4 : (N == 24 ? 8 : (N == 32 ? 2 : (N == 48 ? 4 : 1))));
+    static constexpr int slab_s0 = N == 8 ? 8 : (N == 16 ? 4 : (N == 24 ? 8 : (N == 32 ? 2 : (N == 48 ? 4 : 1))));
+    static constexpr int slab_s = TILE == 1 ? 2 * slab_s0 : slab_s0;
     // lines per pencil block: a multiple of 64 dividing N*N.
-    static constexpr int pencil_nt = N == 8 ? 64 : (N == 24 ? 192 : 256);
+    static constexpr int pencil_nt0 = N == 8 ? 64 : (N == 24 ? 192 : 256);
+    static constexpr int pencil_nt = TILE == 1 ? 128 : (TILE == 2 ? (N == 48 ? 384 : 512) : pencil_nt0);
     // Slab passes keep the next unit's loads in flight in VGPRs (see k_slab) where a
     // line is at most 256 bytes.  For N = 64 (one 16 KB plane per 64-thread block, four
     // sweeps in SLAB_X2X1X1X2) the occupancy is bound by LDS (nine planes per CU), so
@@ -76,10 +85,10 @@ hipError_t launch_cube(const Work& w, double* partials, hipStream_t s)
     }
 }
 
-template <typename T, int N, int M, int G, int CL, int MODE>
+template <typename T, int N, int M, int G, int CL, int MODE, int TILE>
 hipError_t launch_slab(const Work& w, double* partials, hipStream_t s)
 {
-    using Lc = Launch<T, N>;
+    using Lc = Launch<T, N, TILE>;
     constexpr int S = Lc::slab_s;
     constexpr bool PRE = MODE == SLAB_X2X1X1X2 ? Lc::slab_pre_b : Lc::slab_pre;
     constexpr int CP = Lc::slab_cpol;
@@ -91,10 +100,10 @@ hipError_t launch_slab(const Work& w, double* partials, hipStream_t s)
     return launch_persistent<k_slab<T, N, M, G, CL, S, MODE, PRE, false, CP>>(S * N, units, s, w, nullptr);
 }
 
-template <typename T, int N, int M, int G, int CL, int AXIS, int NSW>
+template <typename T, int N, int M, int G, int CL, int AXIS, int NSW, int TILE>
 hipError_t launch_pencil(const Work& w, double* partials, hipStream_t s)
 {
-    using Lc = Launch<T, N>;
+    using Lc = Launch<T, N, TILE>;
     constexpr int NT = Lc::pencil_nt;
     const unsigned grid = (unsigned)(w.first[w.njobs] * (N * N / NT));
     if (AXIS == 2 && partials)
@@ -114,22 +123,24 @@ hipError_t launch_reduce(const Work& w, double* partials, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int N, int M, int G, int CL>
+template <typename T, int N, int M, int G, int CL, int TILE>
 const KernelSet* kernel_set()
 {
-    using Lc = Launch<T, N>;
+    using Lc = Launch<T, N, TILE>;
     static const KernelSet ks = {
         sizeof(T) == 8 ? 1 : 0,
         N,
         M,
         G,
         CL,
-        Lc::cube_fits ? &launch_cube<T, N, M, G, CL> : nullptr,
-        {&launch_slab<T, N, M, G, CL, SLAB_X1>, &launch_slab<T, N, M, G, CL, SLAB_X1X2>,
-         &launch_slab<T, N, M, G, CL, SLAB_X2X1X1X2>, &launch_slab<T, N, M, G, CL, SLAB_X2X1>},
-        &launch_pencil<T, N, M, G, CL, 1, 1>,
-        &launch_pencil<T, N, M, G, CL, 2, 1>,
-        &launch_pencil<T, N, M, G, CL, 2, 2>,
+        TILE,
+        // the cube schedule has one launch shape (tile 0)
+        (TILE == 0 && Lc::cube_fits) ? &launch_cube<T, N, M, G, CL> : nullptr,
+        {&launch_slab<T, N, M, G, CL, SLAB_X1, TILE>, &launch_slab<T, N, M, G, CL, SLAB_X1X2, TILE>,
+         &launch_slab<T, N, M, G, CL, SLAB_X2X1X1X2, TILE>, &launch_slab<T, N, M, G, CL, SLAB_X2X1, TILE>},
+        &launch_pencil<T, N, M, G, CL, 1, 1, TILE>,
+        &launch_pencil<T, N, M, G, CL, 2, 1, TILE>,
+        &launch_pencil<T, N, M, G, CL, 2, 2, TILE>,
         &launch_reduce<T, N>,
         1,
         N * N / Lc::pencil_nt,
@@ -138,6 +149,7 @@ const KernelSet* kernel_set()
     return &ks;
 }
 
-#define CHASM_INSTANTIATE(T, N, M, G, CL) template const KernelSet* kernel_set<T, N, M, G, CL>();
+#define CHASM_INSTANTIATE(T, N, M, G, CL) template const KernelSet* kernel_set<T, N, M, G, CL, 0>();
+#define CHASM_INSTANTIATE_TILE(T, N, M, G, CL, TILE) template const KernelSet* kernel_set<T, N, M, G, CL, TILE>();
 
 }  // namespace chasm

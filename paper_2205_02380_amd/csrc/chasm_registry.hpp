@@ -18,6 +18,7 @@ using LaunchFn = hipError_t (*)(const Work& w, double* partials, hipStream_t str
 struct KernelSet {
     int dtype;              // 0 float, 1 double
     int N, M, G, CL;
+    int tile;               // launch-shape variant (chasm_launch.hpp)
     LaunchFn cube;          // nullptr when the x-cube does not fit in LDS
     // x3-slab passes by sweep sequence: [0] x1, [1] x1 x2, [2] x2 x1 x1 x2 (partials
     // after the first x1), [3] x2 x1 (partials after x1)
@@ -31,7 +32,7 @@ struct KernelSet {
     int slab_rows;          // partial rows per item written by the slab passes
 };
 
-template <typename T, int N, int M, int G, int CL>
+template <typename T, int N, int M, int G, int CL, int TILE>
 const KernelSet* kernel_set();
 
 // (T, N, M, G, CL) shapes, grouped by (N, dtype); the build compiles each shape in a
@@ -62,6 +63,11 @@ const KernelSet* kernel_set();
     X(float, 64, 16, 6, 0) X(float, 64, 16, 8, 0)
 #define CHASM_SHAPES_N48_F64(X) X(double, 48, 16, 8, 0)
 #define CHASM_SHAPES_N64_F64(X) X(double, 64, 16, 8, 0)
+// Shapes compiled in the tile variants 1 and 2 as well (the autotuner's tile-shape
+// axis): the 48^3 FP32 shapes of its patch x ghost sweep, and the 64^3 FP32 shape of
+// the one-GPU-share grid.
+#define CHASM_TILED_SHAPES(X) CHASM_SHAPES_N48_F32(X) X(float, 64, 16, 8, 0)
+constexpr int kTiles = 3;
 #define CHASM_SHAPES(X)                                                                                   \
     CHASM_SHAPES_N8_F32(X) CHASM_SHAPES_N8_F64(X) CHASM_SHAPES_N16_F32(X) CHASM_SHAPES_N16_F64(X)          \
     CHASM_SHAPES_N24_F32(X) CHASM_SHAPES_N24_F64(X) CHASM_SHAPES_N32_F32(X) CHASM_SHAPES_N32_F64(X)        \

@@ -345,8 +345,10 @@ def _large_case(name, steps, nsample, seed, patch=None, ghost=None):
     del f
 
 
-def test_c3_slab_schedule_10_steps():
-    _large_case("C3", 10, 6, 30)
+def test_c3_slab_schedule_50_steps():
+    """C3 over its 50 steps: 14 seeded k-points (1 per mille) against the oracle, every
+    point against the separable reference."""
+    _large_case("C3", 50, 14, 30)
 
 
 @pytest.mark.parametrize("M", [8, 12])
@@ -358,4 +360,7 @@ def test_c3_every_tuning_candidate(M, g):
 
 
 def test_c4_one_gpu_share_50_steps():
-    _large_case("C4", 50, 4, 40)
+    """C4 over its 50 steps (graph-captured): a seeded 1 % sample of the k-points (328
+    x-cubes of 64^3) against the FP64 oracle, every point against the separable
+    reference."""
+    _large_case("C4", 50, 328, 40)

@@ -217,23 +217,50 @@ def test_compiled_shapes_cover_every_tuned_configuration():
         assert n % m == 0 and 1 <= g < n
 
 
-def test_autotune_candidates_weigh_placement():
-    """Every (patch, ghost, schedule) the C3 grid supports appears in place and out of
-    place (48^3 cubes exceed LDS, so no cube schedule)."""
+def test_autotune_candidates_weigh_placement_and_tile_shape():
+    """Every (patch, ghost, schedule, tile) the C3 grid supports appears in place and out
+    of place (48^3 cubes exceed LDS, so no cube schedule); the three tile shapes exist
+    for every 48^3 (patch, ghost)."""
     from paper_2205_02380_amd import autotune
     w = inputs.workload("C3")
     cands = autotune.candidates(w.grid, w.dt, (8, 12, 16), (4, 6, 8), ("cube", "slab", "plain"))
-    keys = {(c["patch"], c["ghost"], c["schedule"]) for c in cands}
+    keys = {(c["patch"], c["ghost"], c["schedule"], c["tile"]) for c in cands}
     assert {c["schedule"] for c in cands} == {"slab", "plain"}
-    assert len(cands) == 2 * len(keys) == 36
+    assert {c["tile"] for c in cands} == {0, 1, 2}
+    assert len(cands) == 2 * len(keys) == 2 * 9 * 2 * 3
+
+
+def _tile_status(grid, M, g, schedule, tile, dtype="f32", runtime=False):
+    flags = chasm.CHASM_FLAG_TILE(tile) | (chasm.CHASM_FLAG_RUNTIME_SHAPE if runtime else 0)
+    try:
+        chasm.chasm_advect_workspace_bytes(chasm.make_desc(grid, M, g, 0.02, dtype, flags=flags, schedule=schedule))
+        return chasm.CHASM_OK
+    except chasm.ChasmError as e:
+        return e.status
+
+
+def test_tile_variant_validation():
+    g48 = inputs.cubic_grid(48, 16.0, 4, 4.0)
+    g64 = inputs.cubic_grid(64, 16.0, 2, 4.0)
+    g32 = inputs.cubic_grid(32, 12.0, 4, 4.0)
+    for t in (0, 1, 2):
+        for sc in ("slab", "plain"):
+            assert _tile_status(g48, 12, 6, sc, t) == chasm.CHASM_OK
+            assert _tile_status(g64, 16, 8, sc, t) == chasm.CHASM_OK
+    assert _tile_status(g48, 12, 6, "auto", 1) == chasm.CHASM_EUNSUPPORTED       # schedule must be named
+    assert _tile_status(g64, 16, 4, "slab", 1) == chasm.CHASM_EUNSUPPORTED       # not compiled in variants
+    assert _tile_status(g32, 8, 6, "slab", 2) == chasm.CHASM_EUNSUPPORTED
+    assert _tile_status(g48, 16, 8, "slab", 1, dtype="f64") == chasm.CHASM_EUNSUPPORTED
+    assert _tile_status(g48, 12, 6, "plain", 1, runtime=True) == chasm.CHASM_EUNSUPPORTED
+    assert _tile_status(g48, 12, 6, "slab", 3) == chasm.CHASM_EINVAL
 
 
 def test_autotune_choice_breaks_timing_ties_by_accuracy():
     from paper_2205_02380_amd import autotune
 
     def c(M, g, sc, oop, ms, dev, ok=True):
-        return {"patch": M, "ghost": g, "schedule": sc, "out_of_place": oop, "ms_per_step": ms, "deviation": dev,
-                "ok": ok}
+        return {"patch": M, "ghost": g, "schedule": sc, "tile": 0, "out_of_place": oop, "ms_per_step": ms,
+                "deviation": dev, "ok": ok}
     cands = [c(16, 8, "slab", False, 4.60, 0.0), c(16, 8, "slab", True, 4.58, 0.0),
              c(12, 8, "slab", False, 4.57, 2.5e-6), c(16, 4, "slab", False, 4.10, 4e-4, ok=False)]
     best = autotune.choose(cands, margin=0.01)

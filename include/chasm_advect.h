@@ -114,7 +114,19 @@ enum {
      * CHASM_EUNSUPPORTED).  The arithmetic does not depend on the variant: results are
      * bitwise equal. */
     CHASM_FLAG_TILE_SHIFT = 4,
-    CHASM_FLAG_TILE_MASK = 3u << 4
+    CHASM_FLAG_TILE_MASK = 3u << 4,
+    /* Observe every call: the x3 sweep that ends the last step of each
+     * chasm_advect_step call with nsteps >= 1 also forms, in its epilogue, the FP64
+     * item rows of the observables of Sec. 5 (W1, W2, W3, P; see
+     * chasm_advect_marginals), and a short pass sums them; chasm_advect_observables
+     * returns them.  That last step runs its sweeps in the order x1, x2, x3 as three
+     * launches (SLAB and CUBE handles included); on a SLAB handle, whose steps
+     * alternate the sweep order, the field it leaves can differ from an unobserved run
+     * in the last bits.  The observables are bitwise equal to chasm_advect_marginals of
+     * the stored field.  The handle allocates the item rows
+     * (nbatch * nk1 nk2 nk3 * (nx1 nx2 + ceil(nx1 nx2 / 64) nx3) doubles) at create.
+     * A handle with this flag is stepped on its own by chasm_advect_step_many. */
+    CHASM_FLAG_OBSERVE = 1u << 6
 };
 #define CHASM_FLAG_TILE(t) ((uint32_t)(t) << CHASM_FLAG_TILE_SHIFT)
 
@@ -190,6 +202,15 @@ chasm_status chasm_advect_diagnostics_noalloc(const chasm_advect_desc* desc, con
  * once; the first call allocates nbatch*nk1*nk2*nk3*(3N + N^2) doubles of device
  * workspace, kept until destroy.  Synchronises the handle's stream. */
 chasm_status chasm_advect_marginals(chasm_advect_t h, double* w1, double* w2, double* w3, double* p12);
+
+/* The observables of the field left by the last chasm_advect_step call (nsteps >= 1)
+ * of a handle created with CHASM_FLAG_OBSERVE, formed in that call's last x3 sweep
+ * (Sec. 5 observables as fused FP64 reductions).  Same layout and values as
+ * chasm_advect_marginals would give on that field, bitwise.  Host pointers, each
+ * nullable; synchronises the stream.  A chasm_advect_marginals call on the handle
+ * reuses the same buffers and replaces them.  CHASM_EINVAL without the flag, before
+ * the first observed call, or after a marginals call until the next observed call. */
+chasm_status chasm_advect_observables(chasm_advect_t h, double* w1, double* w2, double* w3, double* p12);
 
 /* Diagnostics recorded by CHASM_FLAG_REDUCE_EACH_STEP, oldest first:
  * out[s*nbatch*8 + b*8 + i] for s < *n_out (at most max_steps, host memory).

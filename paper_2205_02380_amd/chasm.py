@@ -26,6 +26,7 @@ CHASM_CLOSURE_PMBC, CHASM_CLOSURE_POLY3, CHASM_CLOSURE_NEUMANN, CHASM_CLOSURE_HE
 CHASM_SCHED_AUTO, CHASM_SCHED_CUBE, CHASM_SCHED_SLAB, CHASM_SCHED_PLAIN = 0, 1, 2, 3
 CHASM_FLAG_REDUCE_EACH_STEP, CHASM_FLAG_GRAPH, CHASM_FLAG_OUT_OF_PLACE, CHASM_FLAG_RUNTIME_SHAPE = 1, 2, 4, 8
 CHASM_FLAG_TILE_SHIFT, CHASM_FLAG_TILE_MASK = 4, 3 << 4
+CHASM_FLAG_OBSERVE = 1 << 6
 TILES = (0, 1, 2)
 
 
@@ -72,7 +73,7 @@ EXPORTS = (
     "chasm_advect_create", "chasm_advect_step", "chasm_advect_mass", "chasm_advect_diagnostics",
     "chasm_advect_history", "chasm_advect_step_many", "chasm_advect_workspace_bytes", "chasm_advect_schedule",
     "chasm_advect_destroy", "chasm_advect_last_error", "chasm_advect_version", "chasm_advect_marginals",
-    "chasm_advect_diagnostics_noalloc",
+    "chasm_advect_diagnostics_noalloc", "chasm_advect_observables",
 )
 
 _lib = None
@@ -98,11 +99,12 @@ def lib():
     L.chasm_advect_schedule.argtypes = [vp, ctypes.POINTER(i32)]
     L.chasm_advect_destroy.argtypes = [vp]
     L.chasm_advect_marginals.argtypes = [vp, pd, pd, pd, pd]
+    L.chasm_advect_observables.argtypes = [vp, pd, pd, pd, pd]
     L.chasm_advect_diagnostics_noalloc.argtypes = [pdesc, vp, vp, vp]
     L.chasm_advect_last_error.restype = ctypes.c_char_p
     L.chasm_advect_version.restype = ctypes.c_char_p
     for name in ("create", "step", "mass", "diagnostics", "history", "step_many", "workspace_bytes", "schedule",
-                 "destroy", "marginals", "diagnostics_noalloc"):
+                 "destroy", "marginals", "diagnostics_noalloc", "observables"):
         getattr(L, "chasm_advect_" + name).restype = ctypes.c_int
     _lib = L
     return L
@@ -196,6 +198,15 @@ def chasm_advect_marginals(h: int, grid: Grid, nbatch: int):
     return ws[0], ws[1], ws[2], p
 
 
+def chasm_advect_observables(h: int, grid: Grid, nbatch: int):
+    """(W1, W2, W3, P) formed in the last observed step call (CHASM_FLAG_OBSERVE)."""
+    ws = [np.zeros((nbatch, grid.nk[d], grid.nx[d])) for d in range(3)]
+    p = np.zeros((nbatch, grid.nx[1], grid.nx[0]))
+    ptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().chasm_advect_observables(ctypes.c_void_p(h), ptr(ws[0]), ptr(ws[1]), ptr(ws[2]), ptr(p)))
+    return ws[0], ws[1], ws[2], p
+
+
 def chasm_advect_workspace_bytes(desc: chasm_advect_desc) -> int:
     b = ctypes.c_size_t()
     _check(lib().chasm_advect_workspace_bytes(ctypes.byref(desc), ctypes.byref(b)))
@@ -230,7 +241,7 @@ class Advect:
     def __init__(self, f, grid: Grid, patch, ghost: int, dt: float, closure: str = "pmbc",
                  schedule: str = "auto", reduce_each_step: bool = False, graph: bool = False,
                  history_cap: int = 0, stream=None, out_of_place: bool = False, runtime_shape: bool = False,
-                 slopes=None, tile: int = 0):
+                 slopes=None, tile: int = 0, observe: bool = False):
         import torch
         if not f.is_cuda or not f.is_contiguous():
             raise ValueError("f must be a contiguous device tensor")
@@ -243,7 +254,8 @@ class Advect:
         nbatch = f.numel() // cube
         flags = ((CHASM_FLAG_REDUCE_EACH_STEP if reduce_each_step else 0) | (CHASM_FLAG_GRAPH if graph else 0)
                  | (CHASM_FLAG_OUT_OF_PLACE if out_of_place else 0)
-                 | (CHASM_FLAG_RUNTIME_SHAPE if runtime_shape else 0) | CHASM_FLAG_TILE(tile))
+                 | (CHASM_FLAG_RUNTIME_SHAPE if runtime_shape else 0) | CHASM_FLAG_TILE(tile)
+                 | (CHASM_FLAG_OBSERVE if observe else 0))
         self.desc = make_desc(grid, patch, ghost, dt, dtype, closure, nbatch, flags, schedule, history_cap, slopes)
         self.f = f
         self.nbatch = nbatch
@@ -264,6 +276,10 @@ class Advect:
         """Reduced Wigner functions W1, W2, W3 ([b][k_d][x_d]) and the spatial marginal
         P ([b][x2][x1]) of the current field (Sec. 5), FP64."""
         return chasm_advect_marginals(self.h, self.grid, self.nbatch)
+
+    def observables(self):
+        """(W1, W2, W3, P) formed by the last sweep of the last step call (``observe``)."""
+        return chasm_advect_observables(self.h, self.grid, self.nbatch)
 
     def history(self, max_steps: int = 1 << 20) -> np.ndarray:
         return chasm_advect_history(self.h, self.nbatch, max_steps)

@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/chasm_advect.h"
@@ -205,8 +206,9 @@ struct chasm_advect_s {
     void* tables = nullptr;          // device block: FP64 tables then FP32 mirror, int shifts
     double* partials = nullptr;      // [rows][NRED]
     double* fold = nullptr;          // [nbatch][FOLD_CHUNKS][NRED]
-    double* marg_part = nullptr;     // item rows of the marginals (allocated on first use)
-    double* marg_out = nullptr;
+    double* marg_part = nullptr;     // item rows of the marginals (allocated on first use, or at
+    double* marg_out = nullptr;      //   create with CHASM_FLAG_OBSERVE)
+    bool observed = false;           // marg_out holds the observables of the last step call
     long long partial_rows = 0;      // rows per batch member when reducing each step
     double* last = nullptr;          // [nbatch][NRED]
     double* hist = nullptr;          // [cap][nbatch][NRED]
@@ -282,7 +284,7 @@ static chasm_status validate(const chasm_advect_desc* d, const KernelSet** ks_ou
     if (d->schedule < CHASM_SCHED_AUTO || d->schedule > CHASM_SCHED_PLAIN) return fail(CHASM_EINVAL, "unknown schedule");
     if (d->history_cap < 0) return fail(CHASM_EINVAL, "history_cap must be >= 0");
     if (d->flags & ~(uint32_t)(CHASM_FLAG_REDUCE_EACH_STEP | CHASM_FLAG_GRAPH | CHASM_FLAG_OUT_OF_PLACE |
-                               CHASM_FLAG_RUNTIME_SHAPE | CHASM_FLAG_TILE_MASK))
+                               CHASM_FLAG_RUNTIME_SHAPE | CHASM_FLAG_TILE_MASK | CHASM_FLAG_OBSERVE))
         return fail(CHASM_EINVAL, "unknown flags");
     const int tile = desc_tile(d);
     if (tile >= kTiles) return fail(CHASM_EINVAL, "unknown tile variant");
@@ -413,6 +415,16 @@ static size_t field_bytes(const chasm_advect_desc* d)
     return pts * (d->dtype == CHASM_F64 ? sizeof(double) : sizeof(float));
 }
 
+// Bytes of the observables' item rows and of their sums (marginals and
+// CHASM_FLAG_OBSERVE).
+static std::pair<size_t, size_t> observe_bytes(const chasm_advect_desc* d)
+{
+    const long long nitems = (long long)d->nk[0] * d->nk[1] * d->nk[2] * d->nbatch;
+    const long long per_b = (long long)d->nx[0] * d->nk[0] + (long long)d->nx[1] * d->nk[1] +
+                            (long long)d->nx[2] * d->nk[2] + (long long)d->nx[0] * d->nx[1];
+    return {(size_t)nitems * marginal_row(d->nx) * sizeof(double), (size_t)per_b * d->nbatch * sizeof(double)};
+}
+
 static size_t workspace_bytes(const chasm_advect_desc* d, const KernelSet* ks, int sched, size_t table_bytes)
 {
     const long long nkp = (long long)d->nk[0] * d->nk[1] * d->nk[2];
@@ -425,6 +437,7 @@ static size_t workspace_bytes(const chasm_advect_desc* d, const KernelSet* ks, i
     b += (size_t)d->nbatch * NRED * sizeof(double) + 256;
     if (d->flags & CHASM_FLAG_REDUCE_EACH_STEP) b += (size_t)cap * d->nbatch * NRED * sizeof(double) + 256 + 256;
     if (d->flags & CHASM_FLAG_OUT_OF_PLACE) b += field_bytes(d) + 256;
+    if (d->flags & CHASM_FLAG_OBSERVE) b += observe_bytes(d).first + observe_bytes(d).second + 512;
     return b;
 }
 
@@ -627,6 +640,50 @@ static hipError_t issue_cube_pair(chasm_advect_t h, hipStream_t s)
 
 static bool cube_pairs(const chasm_advect_s* h) { return h->stage && h->schedule == CHASM_SCHED_CUBE; }
 
+// The sums of the observables from the item rows in marg_part; with f given, the
+// separate pass forms the rows from that field first.
+static hipError_t launch_observables(chasm_advect_s* h, const void* f, hipStream_t s)
+{
+    const chasm_advect_desc& d = h->desc;
+    double hx[3], hk[3];
+    for (int a = 0; a < 3; ++a) {
+        hx[a] = (d.x_hi[a] - d.x_lo[a]) / d.nx[a];
+        hk[a] = (d.k_hi[a] - d.k_lo[a]) / d.nk[a];
+    }
+    return launch_marginals(d.dtype, d.nx, d.nk, d.nbatch, hx, hk, f, h->marg_part, h->marg_out, s);
+}
+
+// The last step of an observed call (CHASM_FLAG_OBSERVE): x1, x2, x3 as three launches
+// (the PLAIN form of every schedule's kernels), the x3 launch writing the observables'
+// item rows in its epilogue, then their sums.  Runtime-shape lines the fast kernel form
+// does not serve take the separate row pass instead.  With per-step diagnostics, the
+// step's row comes from a reduction of the stored field.
+static hipError_t issue_observed_step(chasm_advect_t h, hipStream_t s)
+{
+    const bool red = (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) != 0;
+    const int dt = h->desc.dtype;
+    hipError_t e = hipSuccess;
+    bool fused = true;
+    if (h->rt) {
+        for (int a = 0; a < 2 && e == hipSuccess; ++a) e = rt_sweep(h->rtj[a], a, dt, nullptr, s);
+        fused = rt_can_observe(h->rtj[2], dt);
+        if (e == hipSuccess)
+            e = fused ? rt_sweep_obs(h->rtj[2], dt, h->marg_part, s) : rt_sweep(h->rtj[2], 2, dt, nullptr, s);
+        if (e == hipSuccess && red) e = rt_reduce(h->rtj[0], dt, h->partials, s);
+    } else {
+        const Work* pw[3];
+        step_passes(h, pw);
+        e = h->ks->slab[SLAB_X1](*pw[0], nullptr, s);
+        if (e == hipSuccess) e = h->ks->pencil_x2(*pw[1], nullptr, s);
+        if (e == hipSuccess) e = h->ks->pencil_x3_obs(*pw[2], h->marg_part, s);
+        if (e == hipSuccess && red) e = h->ks->reduce(h->work, h->partials, s);
+    }
+    if (e == hipSuccess && red)
+        e = launch_finalize(h, (long long)h->desc.nk[0] * h->desc.nk[1] * h->desc.nk[2], true, s);
+    if (e == hipSuccess) e = launch_observables(h, fused ? nullptr : h->f, s);
+    return e;
+}
+
 // Steps per graph launch for long step counts (CHASM_FLAG_GRAPH): one launch per step
 // leaves a few microseconds between consecutive graphs; within a graph the kernels
 // follow each other directly.
@@ -698,6 +755,12 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
         return bail(CHASM_ENOMEM, "hipMalloc(partials) failed");
     if (hipMalloc((void**)&h->fold, (size_t)desc->nbatch * FOLD_CHUNKS * NRED * sizeof(double)) != hipSuccess)
         return bail(CHASM_ENOMEM, "hipMalloc(fold) failed");
+    if (desc->flags & CHASM_FLAG_OBSERVE) {
+        const auto ob = observe_bytes(desc);
+        if (hipMalloc((void**)&h->marg_part, ob.first) != hipSuccess ||
+            hipMalloc((void**)&h->marg_out, ob.second) != hipSuccess)
+            return bail(CHASM_ENOMEM, "hipMalloc(observable rows) failed");
+    }
     if (hipMalloc((void**)&h->last, (size_t)desc->nbatch * NRED * sizeof(double)) != hipSuccess)
         return bail(CHASM_ENOMEM, "hipMalloc(diagnostics) failed");
     if (desc->flags & CHASM_FLAG_REDUCE_EACH_STEP) {
@@ -809,11 +872,24 @@ chasm_status chasm_advect_create(const chasm_advect_desc* desc, void* f_dev, voi
     return CHASM_OK;
 }
 
+static chasm_status steps_unobserved(chasm_advect_t h, int32_t nsteps);
+
 chasm_status chasm_advect_step(chasm_advect_t h, int32_t nsteps)
 {
     if (!h) return fail(CHASM_EINVAL, "handle is NULL");
     if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
     if (nsteps < 0) return fail(CHASM_EINVAL, "nsteps must be >= 0");
+    if (!(h->desc.flags & CHASM_FLAG_OBSERVE) || nsteps == 0) return steps_unobserved(h, nsteps);
+    chasm_status st = steps_unobserved(h, nsteps - 1);
+    if (st != CHASM_OK) return st;
+    hipError_t e = issue_observed_step(h, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "observed step launch");
+    h->observed = true;
+    return CHASM_OK;
+}
+
+static chasm_status steps_unobserved(chasm_advect_t h, int32_t nsteps)
+{
     if (h->schedule == CHASM_SCHED_SLAB) {
         hipError_t e = slab_steps(h, h->stream, nsteps);
         if (e != hipSuccess) return hip_fail(h, e, "step launch");
@@ -865,7 +941,9 @@ chasm_status chasm_advect_step_many(const chasm_advect_t* hs, int32_t n, const i
     hipStream_t s = n > 0 ? hs[0]->stream : nullptr;
     // Handles that record per-step diagnostics run their call on their own, exactly as
     // chasm_advect_step does.
-    auto alone = [](chasm_advect_t h) { return (h->desc.flags & CHASM_FLAG_REDUCE_EACH_STEP) || h->rt; };
+    auto alone = [](chasm_advect_t h) {
+        return (h->desc.flags & (CHASM_FLAG_REDUCE_EACH_STEP | CHASM_FLAG_OBSERVE)) || h->rt;
+    };
     for (int32_t i = 0; i < n; ++i)
         if (alone(hs[i])) {
             const chasm_status st = chasm_advect_step(hs[i], nsteps[i]);
@@ -1026,28 +1104,43 @@ chasm_status chasm_advect_diagnostics_noalloc(const chasm_advect_desc* desc, con
     return CHASM_OK;
 }
 
+static chasm_status copy_observables(chasm_advect_t h, double* w1, double* w2, double* w3, double* p12);
+
 chasm_status chasm_advect_marginals(chasm_advect_t h, double* w1, double* w2, double* w3, double* p12)
 {
     if (!h) return fail(CHASM_EINVAL, "handle is NULL");
     if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
-    const chasm_advect_desc& d = h->desc;
-    const int N0 = d.nx[0], N1 = d.nx[1], N2 = d.nx[2];
-    const long long nitems = (long long)d.nk[0] * d.nk[1] * d.nk[2] * d.nbatch;
-    const long long per_b = (long long)N0 * d.nk[0] + (long long)N1 * d.nk[1] + (long long)N2 * d.nk[2] +
-                            (long long)N0 * N1;
     if (!h->marg_part) {
-        if (hipMalloc((void**)&h->marg_part, (size_t)nitems * marginal_row(d.nx) * sizeof(double)) != hipSuccess)
+        const auto ob = observe_bytes(&h->desc);
+        if (hipMalloc((void**)&h->marg_part, ob.first) != hipSuccess)
             return fail(CHASM_ENOMEM, "hipMalloc(marginal rows) failed");
-        if (hipMalloc((void**)&h->marg_out, (size_t)per_b * d.nbatch * sizeof(double)) != hipSuccess)
+        if (hipMalloc((void**)&h->marg_out, ob.second) != hipSuccess)
             return fail(CHASM_ENOMEM, "hipMalloc(marginals) failed");
     }
-    double hx[3], hk[3];
-    for (int a = 0; a < 3; ++a) {
-        hx[a] = (d.x_hi[a] - d.x_lo[a]) / d.nx[a];
-        hk[a] = (d.k_hi[a] - d.k_lo[a]) / d.nk[a];
-    }
-    hipError_t e = launch_marginals(d.dtype, d.nx, d.nk, d.nbatch, hx, hk, h->f, h->marg_part, h->marg_out, h->stream);
+    hipError_t e = launch_observables(h, h->f, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "marginals launch");
+    // the buffers now hold this field's marginals, not the last observed call's
+    h->observed = false;
+    return copy_observables(h, w1, w2, w3, p12);
+}
+
+chasm_status chasm_advect_observables(chasm_advect_t h, double* w1, double* w2, double* w3, double* p12)
+{
+    if (!h) return fail(CHASM_EINVAL, "handle is NULL");
+    if (h->poisoned) return fail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
+    if (!(h->desc.flags & CHASM_FLAG_OBSERVE)) return fail(CHASM_EINVAL, "handle was created without CHASM_FLAG_OBSERVE");
+    if (!h->observed) return fail(CHASM_EINVAL, "no observed step since create or the last marginals call");
+    return copy_observables(h, w1, w2, w3, p12);
+}
+
+// Copy the sums in marg_out to the host arrays (stream-ordered, then synchronised).
+static chasm_status copy_observables(chasm_advect_t h, double* w1, double* w2, double* w3, double* p12)
+{
+    const chasm_advect_desc& d = h->desc;
+    const int N0 = d.nx[0], N1 = d.nx[1], N2 = d.nx[2];
+    const long long per_b = (long long)N0 * d.nk[0] + (long long)N1 * d.nk[1] + (long long)N2 * d.nk[2] +
+                            (long long)N0 * N1;
+    hipError_t e;
     std::vector<double> all((size_t)per_b * d.nbatch);
     e = hipMemcpyAsync(all.data(), h->marg_out, all.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

@@ -25,6 +25,7 @@
 #include <stdint.h>
 
 #include "chasm_line.hpp"
+#include "chasm_obs.hpp"
 
 namespace chasm {
 
@@ -568,7 +569,11 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w, double* __restrict
 // N*N so a block never straddles two items.  NSW sweeps along the axis (2: the x3
 // sweep that ends one step and the x3 sweep that starts the next, see SlabMode).
 // RED: FP64 partials of the field after the first sweep, one row per block.
-template <typename T, int N, int M, int G, int CL, int NT, int AXIS, int NSW, bool RED>
+// OBS (one x3 sweep): partials is the item rows of the observables instead; each lane
+// holds its (x1, x2) column after the sweep, so it forms the column sum q and, with
+// the other lanes of its wave (64 consecutive columns), the group plane sums G in the
+// order of chasm_obs.hpp.
+template <typename T, int N, int M, int G, int CL, int NT, int AXIS, int NSW, bool RED, bool OBS = false>
 __global__ __launch_bounds__(NT) void k_pencil(const Work w, double* __restrict__ partials)
 {
     static_assert((N * N) % NT == 0, "block must tile the lines of one item");
@@ -596,6 +601,32 @@ __global__ __launch_bounds__(NT) void k_pencil(const Work w, double* __restrict_
         constexpr int i = decltype(ic)::value;
         v[i] = buf.load<T>(voff, i * sstride);
     });
+    if constexpr (OBS) {
+        static_assert(AXIS == 2 && NSW == 1 && !RED, "observables in the single x3 sweep");
+        T y[N];
+        dispatch_sigma(sigma, [&](auto sc) {
+            constexpr int SIG = decltype(sc)::value;
+            if constexpr (SIG != SIG_ANY) {
+                advect_line<T, N, M, G, CL, SIG>(v, kc, sigma, [&](int j, T x) { y[j] = x; });
+            } else {
+                T cv[N + 7];
+                line_cells<T, N, M, G, CL>(v, cv, kc);
+                store_cells<T, N, SIG_ANY>(cv, sigma, [&](int j, T x) { y[j] = x; });
+            }
+        });
+        double* const row = partials + item * obs_row(N, N, N);
+        double q = 0.0;
+        static_for<0, N>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            obuf.store<T>(y[j], voff, j * sstride);
+            const double x = (double)y[j];
+            q += x;
+            const double gs = obs_wave_sum(x);
+            if ((threadIdx.x & 63) == 0) row[N * N + (L >> 6) * N + j] = gs;
+        });
+        row[L] = q;
+        return;
+    }
     double s = 0.0, s2 = 0.0, sj = 0.0;
     auto tally = [&](int j, T x) {
         if constexpr (RED) {

@@ -114,6 +114,17 @@ hipError_t launch_pencil(const Work& w, double* partials, hipStream_t s)
     return hipGetLastError();
 }
 
+// The x3 sweep that ends an observed step: rows = the observables' item rows.
+template <typename T, int N, int M, int G, int CL, int TILE>
+hipError_t launch_pencil_obs(const Work& w, double* rows, hipStream_t s)
+{
+    using Lc = Launch<T, N, TILE>;
+    constexpr int NT = Lc::pencil_nt;
+    const unsigned grid = (unsigned)(w.first[w.njobs] * (N * N / NT));
+    hipLaunchKernelGGL((k_pencil<T, N, M, G, CL, NT, 2, 1, false, true>), dim3(grid), dim3(NT), 0, s, w, rows);
+    return hipGetLastError();
+}
+
 template <typename T, int N>
 hipError_t launch_reduce(const Work& w, double* partials, hipStream_t s)
 {
@@ -141,6 +152,7 @@ const KernelSet* kernel_set()
         &launch_pencil<T, N, M, G, CL, 1, 1, TILE>,
         &launch_pencil<T, N, M, G, CL, 2, 1, TILE>,
         &launch_pencil<T, N, M, G, CL, 2, 2, TILE>,
+        &launch_pencil_obs<T, N, M, G, CL, TILE>,
         &launch_reduce<T, N>,
         1,
         N * N / Lc::pencil_nt,

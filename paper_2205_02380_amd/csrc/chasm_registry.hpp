@@ -26,6 +26,7 @@ struct KernelSet {
     LaunchFn pencil_x2;
     LaunchFn pencil_x3;     // partials after the x3 sweep
     LaunchFn pencil_x3x3;   // two x3 sweeps, partials after the first
+    LaunchFn pencil_x3_obs; // one x3 sweep writing the observables' item rows (chasm_obs.hpp)
     LaunchFn reduce;        // diagnostics of the current field (one partial row per item)
     int cube_rows;          // partial rows per item written by cube (1)
     int pencil_rows;        // partial rows per item written by the x3 pencils

@@ -33,6 +33,7 @@
 #include "chasm_rt.hpp"
 
 #include "chasm_kernels.hpp"
+#include "chasm_obs.hpp"
 
 namespace chasm {
 
@@ -379,7 +380,10 @@ constexpr int rt_pad() { return GS > 0 ? GS + 4 : 0; }
 // Lines along x1 are rows, and the block's values one contiguous run moved as flat
 // coalesced runs; along x2 and x3, lane = line for the loads and stores (along x2, L is
 // a multiple of n0 when n0 <= 64, so each node's run is whole rows).
-template <typename T, int AXIS, bool RED, int MB, int PW, int GS>
+// OBS (x3 sweep, L = 64): partials is the item rows of the observables; the block's 64
+// lines are one 64-column group of chasm_obs.hpp, so after the sweep its waves form
+// that group's plane sums G and the first wave the column sums q, from the tile.
+template <typename T, int AXIS, bool RED, int MB, int PW, int GS, bool OBS = false>
 __global__ __launch_bounds__(64 * PW) void k_rt_patch(const RtJob j, int L, double* __restrict__ partials)
 {
     constexpr int NT = 64 * PW, LP = kRpLines + 1, PAD = rt_pad<GS>();
@@ -559,16 +563,40 @@ __global__ __launch_bounds__(64 * PW) void k_rt_patch(const RtJob j, int L, doub
         acc[3] = (double)(lg / n0) * acc[0];
         write_partials<NT>(acc, ik, partials + (long long)blk * NRED);
     }
+    if constexpr (OBS) {
+        static_assert(AXIS == 2 && !RED, "observables in the x3 sweep");
+        double* const row = partials + (long long)item * obs_row(n0, n1, N);
+        const long long grp = line0 >> 6;
+        const bool in = ln < nl;
+        for (int z = wv; z < N; z += PW) {
+            const double x = in ? (double)tile[z * LP + ln] : 0.0;
+            const double gs = obs_wave_sum(x);
+            if (ln == 0) row[(long long)n0 * n1 + grp * N + z] = gs;
+        }
+        if (wv == 0 && in) {
+            double q = 0.0;
+            for (int z = 0; z < N; ++z) q += (double)tile[z * LP + ln];
+            row[lg] = q;
+        }
+    }
 }
 
-template <typename T, int AXIS, bool RED, int MB, int GS>
+template <typename T, int AXIS, bool RED, int MB, int GS, bool OBS>
 static void launch_rp(int pw, unsigned grid, size_t lds, hipStream_t s, const RtJob& j, int L, double* partials)
 {
     switch (pw) {
-    case 1: hipLaunchKernelGGL((k_rt_patch<T, AXIS, RED, MB, 1, GS>), dim3(grid), dim3(64), lds, s, j, L, partials); break;
-    case 2: hipLaunchKernelGGL((k_rt_patch<T, AXIS, RED, MB, 2, GS>), dim3(grid), dim3(128), lds, s, j, L, partials); break;
-    case 4: hipLaunchKernelGGL((k_rt_patch<T, AXIS, RED, MB, 4, GS>), dim3(grid), dim3(256), lds, s, j, L, partials); break;
-    default: hipLaunchKernelGGL((k_rt_patch<T, AXIS, RED, MB, 8, GS>), dim3(grid), dim3(512), lds, s, j, L, partials); break;
+    case 1:
+        hipLaunchKernelGGL((k_rt_patch<T, AXIS, RED, MB, 1, GS, OBS>), dim3(grid), dim3(64), lds, s, j, L, partials);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_rt_patch<T, AXIS, RED, MB, 2, GS, OBS>), dim3(grid), dim3(128), lds, s, j, L, partials);
+        break;
+    case 4:
+        hipLaunchKernelGGL((k_rt_patch<T, AXIS, RED, MB, 4, GS, OBS>), dim3(grid), dim3(256), lds, s, j, L, partials);
+        break;
+    default:
+        hipLaunchKernelGGL((k_rt_patch<T, AXIS, RED, MB, 8, GS, OBS>), dim3(grid), dim3(512), lds, s, j, L, partials);
+        break;
     }
 }
 
@@ -593,18 +621,18 @@ static int rp_tile_rows(const RtAxis& a)
     return a.N + 2 * (gs > 0 ? gs + 4 : 0);
 }
 
-template <typename T, int AXIS, bool RED>
+template <typename T, int AXIS, bool RED, bool OBS = false>
 static void launch_rp_mb(const RtAxis& a, int pw, unsigned grid, size_t lds, hipStream_t s, const RtJob& j, int L,
                          double* partials)
 {
     int mb, gs;
     rp_variant(a, mb, gs);
     if (gs == 15)
-        launch_rp<T, AXIS, RED, 15, 15>(pw, grid, lds, s, j, L, partials);
+        launch_rp<T, AXIS, RED, 15, 15, OBS>(pw, grid, lds, s, j, L, partials);
     else if (mb == 16)
-        launch_rp<T, AXIS, RED, 16, 0>(pw, grid, lds, s, j, L, partials);
+        launch_rp<T, AXIS, RED, 16, 0, OBS>(pw, grid, lds, s, j, L, partials);
     else
-        launch_rp<T, AXIS, RED, 64, 0>(pw, grid, lds, s, j, L, partials);
+        launch_rp<T, AXIS, RED, 64, 0, OBS>(pw, grid, lds, s, j, L, partials);
 }
 
 template <typename T>
@@ -647,6 +675,26 @@ static hipError_t rt_sweep_t(const RtJob& j, int axis, double* partials, hipStre
 hipError_t rt_sweep(const RtJob& j, int axis, int dtype, double* partials, hipStream_t s)
 {
     return dtype == 1 ? rt_sweep_t<double>(j, axis, partials, s) : rt_sweep_t<float>(j, axis, partials, s);
+}
+
+bool rt_can_observe(const RtJob& j, int dtype) { return rp_waves(j.ax[2], dtype == 1 ? 8 : 4) != 0; }
+
+template <typename T>
+static hipError_t rt_sweep_obs_t(const RtJob& j, double* rows, hipStream_t s)
+{
+    const RtAxis& a = j.ax[2];
+    const int pw = rp_waves(a, sizeof(T));
+    if (!pw) return hipErrorNotSupported;
+    const int L = kRpLines;
+    const unsigned grid = (unsigned)(j.nitems * ((rt_lines(j, 2) + L - 1) / L));
+    const size_t lds = (size_t)rp_tile_rows(a) * (kRpLines + 1) * sizeof(T);
+    launch_rp_mb<T, 2, false, true>(a, pw, grid, lds, s, j, L, rows);
+    return hipGetLastError();
+}
+
+hipError_t rt_sweep_obs(const RtJob& j, int dtype, double* rows, hipStream_t s)
+{
+    return dtype == 1 ? rt_sweep_obs_t<double>(j, rows, s) : rt_sweep_obs_t<float>(j, rows, s);
 }
 
 // Diagnostics of the current field, one item per block: threads own (x1, x2) columns.

@@ -39,6 +39,12 @@ int rt_lines_per_block(const RtJob& j, int axis, int elem_bytes);
 hipError_t rt_sweep(const RtJob& j, int axis, int dtype, double* partials, hipStream_t s);
 long long rt_rows_per_item(const RtJob& j, int dtype);
 
+// The x3 sweep that ends an observed step, writing the observables' item rows
+// (chasm_obs.hpp) in its epilogue; rt_can_observe: the fast form serves this job (else
+// the observables take the separate pass).
+bool rt_can_observe(const RtJob& j, int dtype);
+hipError_t rt_sweep_obs(const RtJob& j, int dtype, double* rows, hipStream_t s);
+
 // Diagnostics of the current field: one partial row per item.
 hipError_t rt_reduce(const RtJob& j, int dtype, double* partials, hipStream_t s);
 

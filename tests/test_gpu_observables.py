@@ -1,0 +1,125 @@
+"""GPU: the observables of Sec. 5 (reduced Wigner functions W1, W2, W3 and the spatial
+marginal P) as fused FP64 reductions of the x3 sweep that ends an observed step
+(CHASM_FLAG_OBSERVE), on every kernel family: the compiled kernels under the CUBE,
+SLAB and PLAIN schedules (in and out of place, graph replay, batches), and the
+runtime-shape kernels (the unrolled form of the paper's line, the generic form, and
+the general kernel, which takes the separate row pass).
+
+For every case the fused observables are bitwise equal to chasm_advect_marginals of
+the stored field (both form the item rows in the canonical order of chasm_obs.hpp),
+and equal the oracle's integrals of the stored field to 1e-12; with per-step
+diagnostics the observed step's history row matches the oracle's sums.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import observables
+from paper_2205_02380_amd import chasm, inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def grid_of(nx, nk):
+    return inputs.Grid(tuple(nx), tuple(-n / 8.0 for n in nx), tuple(n / 8.0 for n in nx), tuple(nk), (-2.0,) * 3,
+                       (1.8,) * 3)
+
+
+CASES = [  # name, nx, nk, patch, ghost, dtype, kwargs
+    ("cube 16 f32 graph", (16,) * 3, (4, 2, 3), 8, 4, torch.float32, dict(graph=True)),
+    ("cube 16 f64 oop", (16,) * 3, (2, 2, 2), 8, 4, torch.float64, dict(out_of_place=True)),
+    ("slab 48 f32 graph", (48,) * 3, (2, 1, 2), 16, 8, torch.float32, dict(schedule="slab", graph=True)),
+    ("slab 48 f32 tile 1 oop", (48,) * 3, (1, 2, 1), 12, 6, torch.float32,
+     dict(schedule="slab", tile=1, out_of_place=True)),
+    ("plain 32 f64", (32,) * 3, (2, 1, 1), 16, 8, torch.float64, dict(schedule="plain")),
+    ("plain 64 f32", (64,) * 3, (1, 1, 2), 16, 8, torch.float32, dict(schedule="plain")),
+    ("runtime paper line 61", (61,) * 3, (2, 1, 1), 15, 15, torch.float32, dict()),
+    ("runtime 40x48x36 f64", (40, 48, 36), (2, 2, 1), (8, 12, 9), 6, torch.float64, dict(graph=True)),
+    # x3 lines of 140 nodes in patches of 70: the general kernel, rows from the separate pass
+    ("runtime general 41x8x140", (41, 8, 140), (2, 1, 2), (4, 7, 70), 6, torch.float32, dict()),
+]
+
+
+def _oracle_obs(stored, grid):
+    return [observables.marginals(stored[b], grid.hx, grid.hk) for b in range(stored.shape[0])]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("nbatch", [1, 2])
+def test_fused_observables_equal_marginals_and_oracle(case, nbatch):
+    name, nx, nk, patch, ghost, dtype, kw = case
+    if nbatch == 2 and nx[0] >= 61:
+        pytest.skip("batch covered on the smaller grids")
+    grid = grid_of(nx, nk)
+    fields = [inputs.gaussian_field(grid, inputs.random_packets(2, 950 + b, c_range=(-nx[0] / 10, nx[0] / 10),
+                                                                  k0_range=(-0.5, 0.5), s_range=(0.8, 1.2)))
+              for b in range(nbatch)]
+    f = torch.stack(fields).to(dtype).to(DEV).contiguous()
+    say(f"{name} nbatch={nbatch}")
+    with chasm.Advect(f, grid, patch, ghost, 0.1, observe=True, **kw) as a:
+        with pytest.raises(chasm.ChasmError):
+            a.observables()                     # nothing observed yet
+        a.step(3)
+        obs = a.observables()
+        torch.cuda.synchronize()
+        stored = f.double().cpu().numpy()
+        marg = a.marginals()
+        with pytest.raises(chasm.ChasmError):
+            a.observables()                     # the marginals call replaced the buffers
+        a.step(1)                               # a one-step call is observed too
+        obs1 = a.observables()
+        stored1 = f.double().cpu().numpy()
+        marg1 = a.marginals()
+    for got, ref in zip(obs, marg):
+        assert np.array_equal(got, ref)
+    for got, ref in zip(obs1, marg1):
+        assert np.array_equal(got, ref)
+    for b, refs in enumerate(_oracle_obs(stored, grid)):
+        for got, ref in zip(obs, refs):
+            assert got[b].shape == ref.shape
+            assert np.max(np.abs(got[b] - ref)) <= 1e-12 * np.max(np.abs(ref))
+    for b, refs in enumerate(_oracle_obs(stored1, grid)):
+        for got, ref in zip(obs1, refs):
+            assert np.max(np.abs(got[b] - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_observed_steps_with_per_step_diagnostics():
+    """Observation and per-step diagnostics together: one history row per step, the
+    observed step's row from the stored field's sums (oracle, 1e-12)."""
+    grid = grid_of((32,) * 3, (2, 2, 2))
+    f0 = inputs.gaussian_field(grid, inputs.random_packets(3, 960))
+    f = f0.to(torch.float32).to(DEV)
+    with chasm.Advect(f, grid, 8, 6, 0.1, schedule="slab", reduce_each_step=True, observe=True, graph=True) as a:
+        a.step(4)
+        obs = a.observables()
+        hist = a.history()
+        marg = a.marginals()
+    stored = f.double().cpu().numpy()
+    assert hist.shape[0] == 4
+    ref = oracle.reduce(stored, grid.nx, grid.x_lo, grid.hx, grid.nk, grid.k_lo, grid.hk)
+    for i in range(8):
+        assert hist[3, 0, i] == pytest.approx(ref[i], rel=1e-12, abs=1e-14 * abs(ref[0]) * 16)
+    for got, r in zip(obs, marg):
+        assert np.array_equal(got, r)
+
+
+def test_observed_handles_step_alone_in_step_many():
+    grid = grid_of((16,) * 3, (2, 2, 2))
+    fa = inputs.gaussian_field(grid, inputs.random_packets(2, 970)).to(torch.float32).to(DEV)
+    fb = fa.clone()
+    fc = fa.clone()
+    with chasm.Advect(fa, grid, 8, 4, 0.1, observe=True) as a, chasm.Advect(fb, grid, 8, 4, 0.1) as b, \
+            chasm.Advect(fc, grid, 8, 4, 0.1, observe=True) as c:
+        chasm.step_many([a, b], [3, 3])
+        c.step(3)
+        oa, oc = a.observables(), c.observables()
+    torch.cuda.synchronize()
+    assert torch.equal(fa, fc)
+    for x, y in zip(oa, oc):
+        assert np.array_equal(x, y)

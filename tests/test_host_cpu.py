@@ -107,6 +107,21 @@ def test_cube_schedule_rejected_when_cube_exceeds_lds():
     assert 0 < chasm.chasm_advect_workspace_bytes(d) < 64 << 20
 
 
+def test_observe_workspace_adds_the_item_rows():
+    grid = inputs.cubic_grid(32, 12.0, 4, 4.0)
+    d0 = chasm.make_desc(grid, 8, 6, 0.02)
+    d1 = chasm.make_desc(grid, 8, 6, 0.02, flags=chasm.CHASM_FLAG_OBSERVE)
+    nitems = 4 ** 3
+    rows = nitems * (32 * 32 + 16 * 32) * 8
+    sums = (3 * 32 * 4 + 32 * 32) * 8
+    extra = chasm.chasm_advect_workspace_bytes(d1) - chasm.chasm_advect_workspace_bytes(d0)
+    assert rows + sums <= extra <= rows + sums + 1024
+    d2 = chasm.make_desc(grid, 8, 6, 0.02, flags=1 << 7)
+    with pytest.raises(chasm.ChasmError) as ei:
+        chasm.chasm_advect_workspace_bytes(d2)
+    assert ei.value.status == chasm.CHASM_EINVAL
+
+
 def test_out_of_place_workspace_adds_one_field():
     for name, dtype, size in (("C2", "f32", 4), ("C1", "f64", 8)):
         w = inputs.workload(name)

@@ -22,10 +22,10 @@
 // when every read of the tile is done, writes its cell values into the same tile in
 // place: every output node takes exactly one value (from the patch owning its
 // departure cell, or zero beyond the ghosts), so the writes never collide.  The tile
-// then goes back with the same coalesced traversal.  The paper's line (patches of 15
-// cells, n_nb = 15) has a compile-time form: its loops are unrolled without guards and
-// its tile carries zero rows beyond both ends, so each slope is 31 taps at fixed LDS
-// offsets with the coefficients in SGPRs.  Consecutive blocks are dealt to the XCDs so
+// then goes back with the same coalesced traversal.  The paper's lines (n_nb = 15 with
+// patches of 10, 15 or 20 cells) have compile-time forms: their loops are unrolled
+// without guards and their tile carries zero rows beyond both ends, so each slope is 31
+// taps at fixed LDS offsets with the coefficients in SGPRs.  Consecutive blocks are dealt to the XCDs so
 // that neighbouring tiles share an L2.
 //
 // k_rt_sweep (every other shape): one 64-thread block of L <= 64 lines, one line per
@@ -61,10 +61,12 @@ static int rp_waves(const RtAxis& a, int elem_bytes)
     return pw;
 }
 
-// Lines along x2 of k_rt_patch: whole x3-planes (a multiple of n0) when n0 <= 64.
+// Lines along x2 of k_rt_patch: whole x3-planes (a multiple of n0, so each node's run
+// is whole rows) when that fills at least 56 of the 64 lanes; else 64 lines (0 here).
 static int rp_plane_lines(const RtJob& j)
 {
-    return j.nx[0] <= kRpLines ? (kRpLines / j.nx[0]) * j.nx[0] : 0;
+    const int lines = j.nx[0] <= kRpLines ? (kRpLines / j.nx[0]) * j.nx[0] : 0;
+    return lines >= 56 ? lines : 0;
 }
 
 int rt_lines_per_block(const RtJob& j, int axis, int elem_bytes)
@@ -334,6 +336,7 @@ __device__ __forceinline__ RtTail<T> rt_solve_patch(const RtAxis& A, const T* v,
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int i = c + 1 + u;
+                if (i > MB) break;                      // compile-time: the array holds MB + 3
                 if (i <= m) {
                     T r = vv[u];
                     if (i == m) r = fma(T(-1.0 / 3.0), dr, r);
@@ -354,6 +357,7 @@ __device__ __forceinline__ RtTail<T> rt_solve_patch(const RtAxis& A, const T* v,
 #pragma unroll
             for (int u = 15; u >= 0; --u) {
                 const int i = c + u;
+                if (i > MB - 1) continue;               // compile-time, as above
                 if (i <= m - 1) {
                     nxt = fma(-cp[u], nxt, e[i + 1]);
                     e[i + 1] = nxt;
@@ -379,7 +383,7 @@ constexpr int rt_pad() { return GS > 0 ? GS + 4 : 0; }
 // waves; MB >= M bounds the patch length of the register arrays (MB == M: unrolled).
 // Lines along x1 are rows, and the block's values one contiguous run moved as flat
 // coalesced runs; along x2 and x3, lane = line for the loads and stores (along x2, L is
-// a multiple of n0 when n0 <= 64, so each node's run is whole rows).
+// a multiple of n0 when that fills at least 56 lanes, so each node's run is whole rows).
 // OBS (x3 sweep, L = 64): partials is the item rows of the observables; the block's 64
 // lines are one 64-column group of chasm_obs.hpp, so after the sweep its waves form
 // that group's plane sums G and the first wave the column sums q, from the tile.
@@ -600,13 +604,13 @@ static void launch_rp(int pw, unsigned grid, size_t lds, hipStream_t s, const Rt
     }
 }
 
-// Register bound and fixed ghost width of k_rt_patch for an axis: the paper's line
-// (patches of 15 cells, n_nb = 15) unrolled with a padded tile; otherwise MB = 16 or 64
-// with runtime ghost width.
+// Register bound and fixed ghost width of k_rt_patch for an axis: the paper's lines
+// (n_nb = 15 with patches of 10, 15 or 20 cells: the 41-, 61- and 81-node lines of four
+// patches) unrolled with a padded tile; otherwise MB = 16 or 64 with runtime ghost width.
 static void rp_variant(const RtAxis& a, int& mb, int& gs)
 {
-    if (a.M == 15 && a.G == 15) {
-        mb = 15;
+    if (a.G == 15 && (a.M == 10 || a.M == 15 || a.M == 20)) {
+        mb = a.M;
         gs = 15;
     } else {
         mb = a.M <= 16 ? 16 : 64;
@@ -627,8 +631,12 @@ static void launch_rp_mb(const RtAxis& a, int pw, unsigned grid, size_t lds, hip
 {
     int mb, gs;
     rp_variant(a, mb, gs);
-    if (gs == 15)
+    if (gs == 15 && mb == 15)
         launch_rp<T, AXIS, RED, 15, 15, OBS>(pw, grid, lds, s, j, L, partials);
+    else if (gs == 15 && mb == 20)
+        launch_rp<T, AXIS, RED, 20, 15, OBS>(pw, grid, lds, s, j, L, partials);
+    else if (gs == 15 && mb == 10)
+        launch_rp<T, AXIS, RED, 10, 15, OBS>(pw, grid, lds, s, j, L, partials);
     else if (mb == 16)
         launch_rp<T, AXIS, RED, 16, 0, OBS>(pw, grid, lds, s, j, L, partials);
     else

@@ -40,6 +40,7 @@ CASES = [  # name, nx, nk, patch, ghost, dtype, kwargs
     ("plain 32 f64", (32,) * 3, (2, 1, 1), 16, 8, torch.float64, dict(schedule="plain")),
     ("plain 64 f32", (64,) * 3, (1, 1, 2), 16, 8, torch.float32, dict(schedule="plain")),
     ("runtime paper line 61", (61,) * 3, (2, 1, 1), 15, 15, torch.float32, dict()),
+    ("runtime paper lines 81x41x61", (81, 41, 61), (1, 2, 1), (20, 10, 15), 15, torch.float64, dict()),
     ("runtime 40x48x36 f64", (40, 48, 36), (2, 2, 1), (8, 12, 9), 6, torch.float64, dict(graph=True)),
     # x3 lines of 140 nodes in patches of 70: the general kernel, rows from the separate pass
     ("runtime general 41x8x140", (41, 8, 140), (2, 1, 2), (4, 7, 70), 6, torch.float32, dict()),

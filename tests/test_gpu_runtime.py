@@ -38,6 +38,8 @@ def grid_of(nx, nk, kr=2.0):
 
 CASES = [  # (name, nx, nk, patch, ghost, closure, slopes, dt)
     ("paper line 61/15/15", (61, 61, 61), (3, 2, 2), (15, 15, 15), 15, "pmbc", None, 0.1),
+    # the paper's 81- and 41-node lines (four patches of 20 and of 10, n_nb = 15) with a 61
+    ("paper lines 81x41x61", (81, 41, 61), (2, 2, 2), (20, 10, 15), 15, "pmbc", None, 0.1),
     ("anisotropic 40x48x36", (40, 48, 36), (3, 3, 2), (8, 12, 9), 6, "pmbc", None, 0.15),
     ("odd 17x23x31 poly3", (17, 23, 31), (2, 3, 2), (5, 7, 4), 3, "poly3", None, 0.12),
     ("neumann 20x12x28", (20, 12, 28), (3, 2, 3), (6, 4, 9), 4, "neumann", None, 0.1),

@@ -101,14 +101,20 @@ __global__ __launch_bounds__(BigShape<NK>::NTB) void k_thBCD(fft::cd* __restrict
     using B = BigShape<NK>;
     constexpr int P = B::P, L = B::L, S = B::S, RS = B::RS, NT = B::NTB;
     constexpr int JC = NK / 16;                 // 16-output chunks of a Toeplitz row
-    __shared__ cd ACC[NK * RS];                 // [j3][j2]: k2 inverse, summed over residues
+    // N_k = 32: the sum over residues stays in the registers of the thread that owns its
+    // output row j3, and the kernel values K are read from the table (it sits in L2),
+    // so a block needs 34 KB of LDS and four blocks (one wave per SIMD) share a CU;
+    // larger N_k keep the sum and K in LDS.
+    constexpr bool ACC_REG = NK == 32;
+    __shared__ cd ACC[ACC_REG ? 1 : NK * RS];   // [j3][j2]: k2 inverse, summed over residues
     __shared__ cd BC[L * RS];                   // [f][k3]: k2 forward of residue h
     __shared__ cd OC[L * RS];                   // [f][j3]: after the k3 Toeplitz product
-    __shared__ double KK[L * RS];               // [f][q3]: K(xi1, S f + h, q3)
+    __shared__ double KK[ACC_REG ? 1 : L * RS]; // [f][q3]: K(xi1, S f + h, q3)
     const long long xl = blockIdx.x / P;
     const int xi1 = (int)(blockIdx.x % P);
     cd* slice = W + (xl * P + xi1) * (long long)(NK * NK);
     const int tid = threadIdx.x;
+    cd acc[ACC_REG ? NK : 1];                   // row j3 = tid of the residue sum (ACC_REG)
 
     sfor<0, S>([&](auto hc) {
         constexpr int h = decltype(hc)::value;
@@ -124,16 +130,18 @@ __global__ __launch_bounds__(BigShape<NK>::NTB) void k_thBCD(fft::cd* __restrict
             transform<32, -1>(y);
             sfor<0, 32>([&](auto fc) { BC[decltype(fc)::value * RS + r] = y[decltype(fc)::value]; });
         }
-        for (int t = tid; t < L * NK; t += NT) {
-            const int f = t / NK, q = t % NK;
-            KK[f * RS + q] = kt[((long long)xi1 * P + (S * f + h)) * NK + q];
+        if constexpr (!ACC_REG) {
+            for (int t = tid; t < L * NK; t += NT) {
+                const int f = t / NK, q = t % NK;
+                KK[f * RS + q] = kt[((long long)xi1 * P + (S * f + h)) * NK + q];
+            }
         }
         __syncthreads();
         // C: o_j = sum_i K(|j - i|) row_i for each row f, 16 outputs per work item;
         // the 16 kernel values of one input form a window that slides down by one
         for (int t = tid; t < L * JC; t += NT) {
             const int f = t % L, j0 = (t / L) * 16;
-            const double* kk = KK + f * RS;
+            const double* kk = ACC_REG ? kt + ((long long)xi1 * P + (S * f + h)) * NK : KK + f * RS;
             const cd* row = BC + f * RS;
             cd o[16];
             double w[16];
@@ -163,7 +171,8 @@ __global__ __launch_bounds__(BigShape<NK>::NTB) void k_thBCD(fft::cd* __restrict
             sfor<0, 16>([&](auto jc) { OC[f * RS + j0 + decltype(jc)::value] = o[decltype(jc)::value]; });
         }
         __syncthreads();
-        // D: inverse along k2 over this residue's xi2, first NK outputs, summed into ACC
+        // D: inverse along k2 over this residue's xi2, first NK outputs, summed over the
+        // residues (in ACC, or in the registers of thread j3)
         for (int j3 = tid; j3 < NK; j3 += NT) {
             cd v[32];
             sfor<0, 32>([&](auto fc) { v[decltype(fc)::value] = OC[decltype(fc)::value * RS + j3]; });
@@ -171,14 +180,22 @@ __global__ __launch_bounds__(BigShape<NK>::NTB) void k_thBCD(fft::cd* __restrict
             sfor<0, NK>([&](auto jc) {
                 constexpr int j2 = decltype(jc)::value;
                 const cd x = tmul<(long long)h * j2, P, +1>(v[j2 % 32]);
-                ACC[j3 * RS + j2] = h == 0 ? x : cadd(ACC[j3 * RS + j2], x);
+                if constexpr (ACC_REG)
+                    acc[j2] = h == 0 ? x : cadd(acc[j2], x);
+                else
+                    ACC[j3 * RS + j2] = h == 0 ? x : cadd(ACC[j3 * RS + j2], x);
             });
         }
         __syncthreads();
     });
-    for (int t = tid; t < NK * NK; t += NT) {
-        const int j3 = t / NK, j2 = t % NK;
-        slice[t] = ACC[j3 * RS + j2];
+    if constexpr (ACC_REG) {
+        static_assert(!ACC_REG || NT >= NK, "one thread per output row");
+        if (tid < NK) sfor<0, NK>([&](auto jc) { slice[tid * NK + decltype(jc)::value] = acc[decltype(jc)::value]; });
+    } else {
+        for (int t = tid; t < NK * NK; t += NT) {
+            const int j3 = t / NK, j2 = t % NK;
+            slice[t] = ACC[j3 * RS + j2];
+        }
     }
 }
 

@@ -10,12 +10,13 @@
  * tau) and Theta the truncated-kernel operator (chasm_theta_apply), one step is
  *   predictor  f~      = A f^n + tau A Theta[f^n]
  *   corrector  f^{n+1} = A f^n + tau/2 Theta[f~] + tau/2 A Theta[f^n].
- * A is applied once per step to the pair (f^n, Theta[f^n]) as a batch of two fields;
+ * A is applied once per step to f^n and to Theta[f^n] (one advection handle for each);
  * Theta is evaluated twice per step.
  *
  * The field (caller-owned, layout and dtype of chasm_advect.h, nbatch 1) is advanced
- * in place: each chasm_lpc1_step call copies it into the library's state, runs the
- * steps and copies the result back.  Status codes and chasm_advect_last_error() are
+ * in place and is itself the state: the library keeps Theta[f^n] and the predictor in
+ * two fields of its own, and no step copies the field.  If a step fails the handle is
+ * poisoned and the field may hold a partly updated step.  Status codes and chasm_advect_last_error() are
  * shared with chasm_advect.h.  Handles are not thread-safe.
  */
 #ifndef CHASM_LPC1_H
@@ -33,9 +34,9 @@ extern "C" {
 typedef struct chasm_lpc1_s* chasm_lpc1_t;   /* opaque handle */
 
 /* adv describes the grid, splines and tau (= adv->dt); its nbatch must be 1 and its
- * flags 0 (the library steps its own two-field batch).  th must describe the same
- * grid and dtype with nbatch 1.  f_dev is the caller's field.  Allocates three fields
- * of state plus the workspaces of both operators.  CHASM_EINVAL on mismatched
+ * flags 0.  th must describe the same grid and dtype with nbatch 1.  f_dev is the
+ * caller's field; it must stay allocated until chasm_lpc1_destroy.  Allocates two
+ * fields plus the workspaces of the operators (two advection handles, one Theta).  CHASM_EINVAL on mismatched
  * descriptors; the errors of chasm_advect_create / chasm_theta_create otherwise. */
 chasm_status chasm_lpc1_create(const chasm_advect_desc* adv, const chasm_theta_desc* th, void* f_dev,
                                void* hip_stream, chasm_lpc1_t* out);

@@ -2,13 +2,13 @@
 // (chasm_advect.h) and the truncated-kernel Theta_V (chasm_theta.h).  See
 // include/chasm_lpc1.h.
 //
-// State: X = [f, g] (two fields, the batch the advection handle steps), Y (one field).
-// One step:
-//   g = Theta[f]                (theta apply, X0 -> X1)
-//   X = A X                     (one advection launch sequence for both fields)
-//   Y = X0 + tau X1             (predictor)
+// State: the caller's field f, the library's fields G and Y.  One step:
+//   G = Theta[f]                (theta apply, f -> G)
+//   f = A f,  G = A G           (two advection handles on the same stream, one per field)
+//   Y = f + tau G               (predictor)
 //   Y = Theta[Y]                (in place)
-//   X0 = X0 + tau/2 (X1 + Y)    (corrector)
+//   f = f + tau/2 (G + Y)       (corrector)
+// f is stepped in place, so no step copies the field in or out.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,11 +42,12 @@ __global__ __launch_bounds__(256) void k_lpc1_combine(T* __restrict__ x0, const 
 using namespace chasm;
 
 struct chasm_lpc1_s {
-    chasm_advect_t adv = nullptr;
+    chasm_advect_t adv_f = nullptr;   // characteristic step of the caller's field
+    chasm_advect_t adv_g = nullptr;   // characteristic step of G
     chasm_theta_t th = nullptr;
     void* f = nullptr;          // caller's field
-    void* X = nullptr;          // [2][field]
-    void* Y = nullptr;          // [field]
+    void* G = nullptr;          // [field]: Theta[f^n], then A Theta[f^n]
+    void* Y = nullptr;          // [field]: the predictor
     hipStream_t stream = nullptr;
     int dtype = 0;
     long long n = 0;            // values per field
@@ -102,11 +103,10 @@ chasm_status chasm_lpc1_create(const chasm_advect_desc* adv, const chasm_theta_d
         chasm_lpc1_destroy(h);
         return lfail(s, m);
     };
-    if (hipMalloc(&h->X, 2 * bytes) != hipSuccess) return bail(CHASM_ENOMEM, "hipMalloc(state) failed");
+    if (hipMalloc(&h->G, bytes) != hipSuccess) return bail(CHASM_ENOMEM, "hipMalloc(theta field) failed");
     if (hipMalloc(&h->Y, bytes) != hipSuccess) return bail(CHASM_ENOMEM, "hipMalloc(predictor) failed");
-    chasm_advect_desc ad = *adv;
-    ad.nbatch = 2;
-    chasm_status st = chasm_advect_create(&ad, h->X, hip_stream, &h->adv);
+    chasm_status st = chasm_advect_create(adv, f_dev, hip_stream, &h->adv_f);
+    if (st == CHASM_OK) st = chasm_advect_create(adv, h->G, hip_stream, &h->adv_g);
     if (st != CHASM_OK) {
         const std::string m = chasm_advect_last_error();
         return bail(st, "advection: " + m);
@@ -126,31 +126,26 @@ chasm_status chasm_lpc1_step(chasm_lpc1_t h, int32_t nsteps)
     if (h->poisoned) return lfail(CHASM_ESTATE, "handle is poisoned by an earlier device failure");
     if (nsteps < 0) return lfail(CHASM_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return CHASM_OK;
-    const size_t bytes = (size_t)h->n * (h->dtype == CHASM_F64 ? 8 : 4);
-    char* x0 = static_cast<char*>(h->X);
-    char* x1 = x0 + bytes;
     auto dev = [&](hipError_t e, const char* what) {
         h->poisoned = true;
         return lfail(CHASM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
-    hipError_t e = hipMemcpyAsync(x0, h->f, bytes, hipMemcpyDeviceToDevice, h->stream);
-    if (e != hipSuccess) return dev(e, "state copy");
+    hipError_t e;
     for (int s = 0; s < nsteps; ++s) {
-        chasm_status st = chasm_theta_apply(h->th, x0, x1);
-        if (st == CHASM_OK) st = chasm_advect_step(h->adv, 1);
+        chasm_status st = chasm_theta_apply(h->th, h->f, h->G);
+        if (st == CHASM_OK) st = chasm_advect_step(h->adv_f, 1);
+        if (st == CHASM_OK) st = chasm_advect_step(h->adv_g, 1);
         if (st != CHASM_OK) {
             h->poisoned = true;
             return st;
         }
-        if ((e = combine(h, x0, x1, h->Y, h->tau, 0)) != hipSuccess) return dev(e, "predictor");
+        if ((e = combine(h, h->f, h->G, h->Y, h->tau, 0)) != hipSuccess) return dev(e, "predictor");
         if ((st = chasm_theta_apply(h->th, h->Y, h->Y)) != CHASM_OK) {
             h->poisoned = true;
             return st;
         }
-        if ((e = combine(h, x0, x1, h->Y, 0.5 * h->tau, 1)) != hipSuccess) return dev(e, "corrector");
+        if ((e = combine(h, h->f, h->G, h->Y, 0.5 * h->tau, 1)) != hipSuccess) return dev(e, "corrector");
     }
-    e = hipMemcpyAsync(h->f, x0, bytes, hipMemcpyDeviceToDevice, h->stream);
-    if (e != hipSuccess) return dev(e, "result copy");
     return CHASM_OK;
 }
 
@@ -158,9 +153,10 @@ chasm_status chasm_lpc1_destroy(chasm_lpc1_t h)
 {
     if (!h) return CHASM_OK;
     if (h->stream) hipStreamSynchronize(h->stream);
-    if (h->adv) chasm_advect_destroy(h->adv);
+    if (h->adv_f) chasm_advect_destroy(h->adv_f);
+    if (h->adv_g) chasm_advect_destroy(h->adv_g);
     if (h->th) chasm_theta_destroy(h->th);
-    if (h->X) hipFree(h->X);
+    if (h->G) hipFree(h->G);
     if (h->Y) hipFree(h->Y);
     delete h;
     return CHASM_OK;

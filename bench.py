@@ -197,7 +197,8 @@ def bench_large(args, name):
     copy_gbs = copy_bandwidth(torch, dev)
     tuning = None
     if name == "C3" and not args.no_tune:
-        res = autotune.tune(w.grid, w.dt, w.packets, steps=5, tol=1e-5,
+        # timed as the run below: graph-replayed, FP64 diagnostics every step
+        res = autotune.tune(w.grid, w.dt, w.packets, steps=5, tol=1e-5, reduce_each_step=True,
                             log=lambda m: print(m, file=sys.stderr, flush=True))
         b = res["best"]
         tuning = {"best": b, "candidates": len(res["candidates"]),

@@ -12,7 +12,11 @@ the fastest candidate whose result stays within `tol` (relative to max|f|) of th
 reference; candidates within `margin` (relative) of the fastest time count as equally
 fast (timing noise on a few steps is about 1 %), and among them the most accurate one
 wins (in place is listed before out of place, so the second field is taken only when
-it is faster by more than the margin).  Results can be cached in a JSON file keyed by the grid and dt.
+it is faster by more than the margin).  Candidates are timed with the per-step FP64
+diagnostics on when the run they are tuned for records them (`reduce_each_step`): the
+reduction epilogue changes a pass's register use, so the fastest launch shape with it
+can differ from the fastest without it.  Results can be cached in a JSON file keyed by
+the grid and dt.
 
 Host logic only: every step runs through the C ABI.  Parity of each compiled (M, g)
 with the FP64 oracle is the test suite's job, not the tuner's.
@@ -66,7 +70,8 @@ def choose(cands: List[dict], margin: float = 0.01) -> dict:
 
 def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 16), ghosts=(4, 6, 8),
          schedules=("cube", "slab", "plain"), placements=(False, True), tiles=chasm.TILES, steps: int = 5,
-         warmup: int = 2, tol: float = 1e-5, margin: float = 0.01, device: str = "cuda:0", log=None) -> dict:
+         warmup: int = 2, tol: float = 1e-5, margin: float = 0.01, device: str = "cuda:0", log=None,
+         reduce_each_step: bool = False) -> dict:
     import torch
     dev = torch.device(device)
     stream = torch.cuda.current_stream(dev)
@@ -84,7 +89,8 @@ def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 
     for c in cands:
         work.copy_(f0)
         adv = chasm.Advect(work, grid, c["patch"], c["ghost"], dt, schedule=c["schedule"], graph=True,
-                           stream=stream, out_of_place=c["out_of_place"], tile=c["tile"])
+                           stream=stream, out_of_place=c["out_of_place"], tile=c["tile"],
+                           reduce_each_step=reduce_each_step, history_cap=warmup + steps)
         adv.step(warmup)
         torch.cuda.synchronize()
         work.copy_(f0)
@@ -112,11 +118,11 @@ def tune(grid: inputs.Grid, dt: float, packets: inputs.Packets, patches=(8, 12, 
     torch.cuda.empty_cache()
     best = choose(cands, margin)
     return {"grid": {"nx": list(grid.nx), "nk": list(grid.nk)}, "dt": dt, "tol": tol, "steps": steps,
-            "candidates": cands, "best": best}
+            "reduce_each_step": reduce_each_step, "candidates": cands, "best": best}
 
 
-def cache_key(grid: inputs.Grid, dt: float) -> str:
-    return f"nx{grid.nx[0]}_nk{grid.nk[0]}x{grid.nk[1]}x{grid.nk[2]}_dt{dt:g}"
+def cache_key(grid: inputs.Grid, dt: float, reduce_each_step: bool = False) -> str:
+    return f"nx{grid.nx[0]}_nk{grid.nk[0]}x{grid.nk[1]}x{grid.nk[2]}_dt{dt:g}" + ("_red" if reduce_each_step else "")
 
 
 def load_cache(path: str) -> Dict[str, dict]:
@@ -126,13 +132,13 @@ def load_cache(path: str) -> Dict[str, dict]:
     return {}
 
 
-def lookup(path: str, grid: inputs.Grid, dt: float) -> Optional[dict]:
-    return load_cache(path).get(cache_key(grid, dt))
+def lookup(path: str, grid: inputs.Grid, dt: float, reduce_each_step: bool = False) -> Optional[dict]:
+    return load_cache(path).get(cache_key(grid, dt, reduce_each_step))
 
 
 def store(path: str, grid: inputs.Grid, dt: float, result: dict) -> None:
     c = load_cache(path)
-    c[cache_key(grid, dt)] = result
+    c[cache_key(grid, dt, bool(result.get("reduce_each_step", False)))] = result
     with open(path, "w") as fh:
         json.dump(c, fh, indent=1)
 
@@ -143,9 +149,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--cache", default="")
+    ap.add_argument("--reduce-each-step", action="store_true", help="time with the per-step FP64 diagnostics")
     args = ap.parse_args()
     w = inputs.workload(args.workload)
-    res = tune(w.grid, w.dt, w.packets, steps=args.steps, tol=args.tol, log=print)
+    res = tune(w.grid, w.dt, w.packets, steps=args.steps, tol=args.tol, log=print,
+               reduce_each_step=args.reduce_each_step)
     print(json.dumps(res["best"]))
     if args.cache:
         store(args.cache, w.grid, w.dt, res)

@@ -502,25 +502,53 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w, double* __restrict
             __syncthreads();
         }
         {   // x1 on the rows (x2, slab) = (col_t, slab_t), once or (SLAB_X2X1X1X2) twice.
-            // The two x1 sweeps of SLAB_X2X1X1X2 run back to back through this thread's
-            // own LDS row (no other thread touches it, so no barrier between them), as a
-            // loop kept rolled so that the compiler never holds two lines at once.
+            // No other thread touches this thread's LDS row, so the two x1 sweeps of
+            // SLAB_X2X1X1X2 need no barrier between them.  X1REG (FP32, N <= 48): the
+            // intermediate line stays in registers as in k_pencil's two-sweep form (the
+            // first sweep's cells for other shifts through the compile-time barrel
+            // shifter), which saves a store and a load of the row per lane; the step's
+            // partials are tallied from those registers in ascending x1, the order of
+            // the LDS form.  Otherwise (FP64 lines, and N = 64, whose tuned
+            // prefetching pass holds the next unit in VGPRs) the two sweeps run through
+            // the LDS row as a loop kept rolled, so no two lines are live at once.
             int sigma;
             const auto kc = axis_coef<T>(job, 0, ik[0], sigma);
             T* row = lds + threadIdx.x * PX;
-            constexpr int NX1 = MODE == SLAB_X2X1X1X2 ? 2 : 1;
-#pragma unroll 1
-            for (int pass = 0; pass < NX1; ++pass) {
+            constexpr bool X1REG = MODE == SLAB_X2X1X1X2 && sizeof(T) == 4 && N <= 48;
+            if constexpr (X1REG) {
                 dispatch_sigma(sigma, [&](auto sc) {
-                    T v[N];
+                    constexpr int SIG = decltype(sc)::value;
+                    T v[N], y[N];
 #pragma unroll
                     for (int i = 0; i < N; ++i) v[i] = row[i];
-                    advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { row[j] = x; });
-                });
-                if constexpr (RED) {
-                    if (pass == 0) {   // the step ends after the first x1 sweep
+                    if constexpr (SIG != SIG_ANY) {
+                        advect_line<T, N, M, G, CL, SIG>(v, kc, sigma, [&](int j, T x) { y[j] = x; });
+                    } else {
+                        T cv[N + 7];
+                        line_cells<T, N, M, G, CL>(v, cv, kc);
+                        store_cells<T, N, SIG_ANY>(cv, sigma, [&](int j, T x) { y[j] = x; });
+                    }
+                    if constexpr (RED) {   // the step ends after the first x1 sweep
 #pragma unroll
-                        for (int i = 0; i < N; ++i) tally(i, row[i]);
+                        for (int i = 0; i < N; ++i) tally(i, y[i]);
+                    }
+                    advect_line<T, N, M, G, CL, SIG>(y, kc, sigma, [&](int j, T x) { row[j] = x; });
+                });
+            } else {
+                constexpr int NX1 = MODE == SLAB_X2X1X1X2 ? 2 : 1;
+#pragma unroll 1
+                for (int pass = 0; pass < NX1; ++pass) {
+                    dispatch_sigma(sigma, [&](auto sc) {
+                        T v[N];
+#pragma unroll
+                        for (int i = 0; i < N; ++i) v[i] = row[i];
+                        advect_line<T, N, M, G, CL, decltype(sc)::value>(v, kc, sigma, [&](int j, T x) { row[j] = x; });
+                    });
+                    if constexpr (RED) {
+                        if (pass == 0) {   // the step ends after the first x1 sweep
+#pragma unroll
+                            for (int i = 0; i < N; ++i) tally(i, row[i]);
+                        }
                     }
                 }
             }

@@ -287,3 +287,17 @@ def test_autotune_choice_breaks_timing_ties_by_accuracy():
     assert autotune.choose(cands, margin=0.01)["out_of_place"] is True
     with pytest.raises(ValueError):
         autotune.choose([c(8, 4, "slab", False, 1.0, 1.0, ok=False)])
+
+
+def test_autotune_cache_keys_keep_reduction_runs_apart(tmp_path):
+    # a result tuned with the per-step diagnostics is cached apart from one tuned without
+    from paper_2205_02380_amd import autotune
+    w = inputs.workload("C3")
+    path = str(tmp_path / "tune.json")
+    plain = {"reduce_each_step": False, "best": {"tile": 1}}
+    red = {"reduce_each_step": True, "best": {"tile": 0}}
+    autotune.store(path, w.grid, w.dt, plain)
+    autotune.store(path, w.grid, w.dt, red)
+    assert autotune.lookup(path, w.grid, w.dt)["best"]["tile"] == 1
+    assert autotune.lookup(path, w.grid, w.dt, reduce_each_step=True)["best"]["tile"] == 0
+    assert autotune.cache_key(w.grid, w.dt) != autotune.cache_key(w.grid, w.dt, True)

@@ -503,18 +503,17 @@ __global__ __launch_bounds__(S * N) void k_slab(const Work w, double* __restrict
         }
         {   // x1 on the rows (x2, slab) = (col_t, slab_t), once or (SLAB_X2X1X1X2) twice.
             // No other thread touches this thread's LDS row, so the two x1 sweeps of
-            // SLAB_X2X1X1X2 need no barrier between them.  X1REG (FP32, N <= 48): the
+            // SLAB_X2X1X1X2 need no barrier between them.  X1REG (FP32, N <= 64): the
             // intermediate line stays in registers as in k_pencil's two-sweep form (the
             // first sweep's cells for other shifts through the compile-time barrel
             // shifter), which saves a store and a load of the row per lane; the step's
             // partials are tallied from those registers in ascending x1, the order of
-            // the LDS form.  Otherwise (FP64 lines, and N = 64, whose tuned
-            // prefetching pass holds the next unit in VGPRs) the two sweeps run through
-            // the LDS row as a loop kept rolled, so no two lines are live at once.
+            // the LDS form.  Otherwise (FP64 lines) the two sweeps run through the LDS
+            // row as a loop kept rolled, so no two lines are live at once.
             int sigma;
             const auto kc = axis_coef<T>(job, 0, ik[0], sigma);
             T* row = lds + threadIdx.x * PX;
-            constexpr bool X1REG = MODE == SLAB_X2X1X1X2 && sizeof(T) == 4 && N <= 48;
+            constexpr bool X1REG = MODE == SLAB_X2X1X1X2 && sizeof(T) == 4 && N <= 64;
             if constexpr (X1REG) {
                 dispatch_sigma(sigma, [&](auto sc) {
                     constexpr int SIG = decltype(sc)::value;

@@ -31,15 +31,15 @@ struct Launch {
     static constexpr int pencil_nt0 = N == 8 ? 64 : (N == 24 ? 192 : 256);
     static constexpr int pencil_nt = TILE == 1 ? 128 : (TILE == 2 ? (N == 48 ? 384 : 512) : pencil_nt0);
     // Slab passes keep the next unit's loads in flight in VGPRs (see k_slab) where a
-    // line is at most 256 bytes.  For N = 64 (one 16 KB plane per 64-thread block, four
-    // sweeps in SLAB_X2X1X1X2) the occupancy is bound by LDS (nine planes per CU), so
-    // the prefetch costs nothing and hides the next plane's latency: 14.9 -> 13.7 ms per
-    // pass on the 64^3 x 32^3 grid, with streamed (nontemporal) field accesses
-    // (slab_cpol) a further 2 %.  For N = 48 (four planes per block) the four-sweep pass
-    // is faster without the prefetch (3 waves per SIMD instead of 2) and with default
-    // caching (2.55 ms against 2.65-2.85 ms for the other three forms).
+    // line is at most 256 bytes, except the four-sweep pass (SLAB_X2X1X1X2), whose VGPRs
+    // go to the register-resident x1 pair instead (see k_slab).  At N = 64 (one 16 KB
+    // plane per 64-thread block, occupancy bound by LDS at nine planes per CU) the
+    // prefetch had taken that pass from 14.9 to 13.7 ms on the 64^3 x 32^3 grid with the
+    // x1 pair through LDS; the register pair without the prefetch is faster again (13.0
+    // -> 12.9 ms per step with per-step reductions), and with the prefetch as well it
+    // needs 256 VGPRs (one wave per SIMD).  Streamed (nontemporal) field accesses at
+    // N = 64 (slab_cpol) gain a further 2 %; at N = 48 default caching is faster.
     static constexpr bool slab_pre = sizeof(T) * N <= 256;
-    static constexpr bool slab_pre_b = sizeof(T) == 4 && N == 64;
     static constexpr int slab_cpol = N == 64 ? kCpolStream : 0;
     static constexpr int reduce_nt = 256;
 };
@@ -90,7 +90,7 @@ hipError_t launch_slab(const Work& w, double* partials, hipStream_t s)
 {
     using Lc = Launch<T, N, TILE>;
     constexpr int S = Lc::slab_s;
-    constexpr bool PRE = MODE == SLAB_X2X1X1X2 ? Lc::slab_pre_b : Lc::slab_pre;
+    constexpr bool PRE = MODE != SLAB_X2X1X1X2 && Lc::slab_pre;
     constexpr int CP = Lc::slab_cpol;
     const long long units = w.first[w.njobs] * (N / S);
     if constexpr (MODE == SLAB_X2X1X1X2 || MODE == SLAB_X2X1) {

@@ -183,6 +183,15 @@ __device__ __forceinline__ AxisCoef<T> axis_coef(const JobDev& job, int d, int i
     return c;
 }
 
+// One DPP lane move of a double (both halves, every lane written).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // Sum NV doubles over the block; thread 0 ends up with the totals in acc.
 template <int NT, int NV>
 __device__ __forceinline__ void block_sum(double (&acc)[NV])
@@ -190,9 +199,16 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV])
     __shared__ double red[NT / 64][NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
+        // within each row of 16 lanes by DPP moves (VALU): pairs, quads, then the
+        // half-row and row mirrors, which pair lanes of groups already summed; across
+        // rows by two lane permutes
         double x = acc[v];
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+        x += dpp_f64<0xB1>(x);    // quad_perm [1,0,3,2]
+        x += dpp_f64<0x4E>(x);    // quad_perm [2,3,0,1]
+        x += dpp_f64<0x141>(x);   // row_half_mirror
+        x += dpp_f64<0x140>(x);   // row_mirror
+        x += __shfl_xor(x, 16, 64);
+        x += __shfl_xor(x, 32, 64);
         acc[v] = x;
     }
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
